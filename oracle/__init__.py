@@ -1,0 +1,180 @@
+"""Python access to the exact CPU oracle (oracle/vcm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The library's compute path never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libvcm_oracle.so")
+_lib = None
+
+
+class VoTarget(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("normal_axis", ctypes.c_int),
+                ("normal_sign", ctypes.c_int), ("su", ctypes.c_int), ("sv", ctypes.c_int),
+                ("center", ctypes.c_double * 3), ("size", ctypes.c_double * 2)]
+
+
+class VoGrid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("extent", ctypes.c_double * 3),
+                ("n", ctypes.c_int64 * 3)]
+
+
+class VoParams(ctypes.Structure):
+    _fields_ = [("mu_arcmin", ctypes.c_double), ("d0", ctypes.c_double),
+                ("fov_deg", ctypes.c_double), ("n_bins", ctypes.c_int),
+                ("bin_scale", ctypes.c_int), ("mode", ctypes.c_int)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.vo_segment_meets_box.argtypes = [ctypes.c_int, dp, dp, dp, dp]
+        L.vo_segment_meets_box.restype = ctypes.c_int
+        L.vo_live_samples.argtypes = [ctypes.POINTER(VoTarget), dp, dp]
+        L.vo_live_samples.restype = ctypes.c_int
+        L.vo_measure.argtypes = [ctypes.POINTER(VoTarget), ctypes.POINTER(VoParams), dp, dp]
+        L.vo_measure.restype = None
+        L.vo_in_fov.argtypes = [ctypes.POINTER(VoTarget), ctypes.POINTER(VoParams), dp]
+        L.vo_in_fov.restype = ctypes.c_int
+        L.vo_eval.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp,
+                              ctypes.POINTER(VoTarget), ctypes.POINTER(VoGrid),
+                              ctypes.POINTER(VoParams), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.c_int64, ctypes.c_int,
+                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.vo_eval.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _vec3(x):
+    a = np.zeros(3, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64).ravel()
+    a[: len(x)] = x
+    return a
+
+
+def make_target(t) -> VoTarget:
+    T = VoTarget()
+    T.kind = int(t.kind)
+    T.normal_axis = int(t.normal_axis)
+    T.normal_sign = int(t.normal_sign)
+    T.su = int(t.samples_u)
+    T.sv = int(t.samples_v)
+    for k in range(3):
+        T.center[k] = float(t.center[k])
+    T.size[0] = float(t.size[0])
+    T.size[1] = float(t.size[1])
+    return T
+
+
+def make_grid(g) -> VoGrid:
+    G = VoGrid()
+    for k in range(3):
+        G.origin[k] = float(g.origin[k])
+        G.extent[k] = float(g.extent[k])
+        G.n[k] = int(g.n[k])
+    return G
+
+
+def make_params(p) -> VoParams:
+    P = VoParams()
+    P.mu_arcmin = float(p.mu_arcmin)
+    P.d0 = float(p.near_d0)
+    P.fov_deg = float(p.fov_deg)
+    P.n_bins = int(p.n_bins)
+    P.bin_scale = int(p.bin_scale)
+    P.mode = int(p.mode)
+    return P
+
+
+def segment_meets_box(q, s, lo, hi, dim=3) -> int:
+    q, s, lo, hi = (_vec3(v) for v in (q, s, lo, hi))
+    r = lib().vo_segment_meets_box(int(dim), _dptr(q), _dptr(s), _dptr(lo), _dptr(hi))
+    if r < 0:
+        raise ValueError("inputs must be multiples of 2^-8 with lo <= hi")
+    return r
+
+
+def live_samples(target, q) -> np.ndarray:
+    T = make_target(target)
+    q = _vec3(q)
+    out = np.zeros((6 * target.samples_u * target.samples_v, 3), dtype=np.float64)
+    n = lib().vo_live_samples(ctypes.byref(T), _dptr(q), _dptr(out))
+    return out[:n].copy()
+
+
+def measure(target, params, q) -> Dict[str, float]:
+    T, P = make_target(target), make_params(params)
+    q = _vec3(q)
+    out = np.zeros(4, dtype=np.float64)
+    lib().vo_measure(ctypes.byref(T), ctypes.byref(P), _dptr(q), _dptr(out))
+    return {"D": out[0], "alpha": out[1], "V": out[2], "V0": out[3]}
+
+
+def in_fov(target, params, q) -> bool:
+    T, P = make_target(target), make_params(params)
+    q = _vec3(q)
+    return bool(lib().vo_in_fov(ctypes.byref(T), ctypes.byref(P), _dptr(q)))
+
+
+def vcm_eval(scene, query, vp_index: Optional[np.ndarray] = None, nthreads: int = 1,
+             mode: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """Oracle VCM at the listed viewpoint indices (default: the whole grid)."""
+    g = query.grid
+    if vp_index is None:
+        vp_index = np.arange(g.count, dtype=np.int64)
+    vp = np.ascontiguousarray(vp_index, dtype=np.int64)
+    n = len(vp)
+    lo = np.ascontiguousarray(scene.lo, dtype=np.float64)
+    hi = np.ascontiguousarray(scene.hi, dtype=np.float64)
+    T, G, P = make_target(query.target), make_grid(g), make_params(query.params)
+    if mode is not None:
+        P.mode = int(mode)
+    out = {
+        "count": np.zeros(n, dtype=np.uint16),
+        "nlive": np.zeros(n, dtype=np.uint16),
+        "infov": np.zeros(n, dtype=np.uint8),
+        "c": np.zeros(n, dtype=np.float64),
+        "cb": np.zeros(n, dtype=np.float64),
+        "bin": np.zeros(n, dtype=np.uint8),
+    }
+    r = lib().vo_eval(int(scene.dim), int(scene.n), _dptr(lo), _dptr(hi),
+                      ctypes.byref(T), ctypes.byref(G), ctypes.byref(P),
+                      vp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n, int(nthreads),
+                      out["count"].ctypes.data, out["nlive"].ctypes.data,
+                      out["infov"].ctypes.data, out["c"].ctypes.data,
+                      out["cb"].ctypes.data, out["bin"].ctypes.data)
+    if r != 0:
+        raise ValueError("oracle rejected the query (non-dyadic or invalid input)")
+    return out
+
+
+def viewpoint_coords(grid, vp_index) -> np.ndarray:
+    """Cell-centred viewpoint coordinates (x fastest), as the oracle forms them."""
+    vp = np.asarray(vp_index, dtype=np.int64)
+    nx, ny, nz = (int(v) for v in grid.n)
+    ii = np.stack([vp % nx, (vp // nx) % ny, vp // (nx * ny)])
+    out = np.zeros((len(vp), 3))
+    for a in range(3):
+        if grid.extent[a] == 0 and grid.n[a] == 1:
+            continue
+        out[:, a] = grid.origin[a] + (2 * ii[a] + 1) * (grid.extent[a] / (2.0 * grid.n[a]))
+    return out

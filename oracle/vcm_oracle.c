@@ -1,0 +1,488 @@
+/*
+ * vcm_oracle.c -- plain, slow, exact CPU reference for target-centric
+ * visibility color maps (VCM).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  The HIP library
+ * shares no code with it and never calls it.
+ *
+ * What it computes, with the passage each part follows:
+ *   - VCM (Def. 2.1): one colour c in [0,1] per viewpoint of a discretised
+ *     space, for a given target T and obstacle set O.
+ *   - Point-to-point visibility (Def. 2.2): p and p' see each other iff the
+ *     segment pp' meets no obstacle.  Obstacles are closed axis-aligned boxes
+ *     and touching counts as meeting (Def. 3.1 says a segment that touches an
+ *     obstacle is shadowed).  The test is exact: every input is a multiple of
+ *     2^-8 below 2^14 in magnitude, so it runs in 64-bit integers.
+ *   - Obstructed region (Def. 2.3): a viewpoint that does not see *all* points
+ *     of T is obstructed and coloured 0 (Sec. III-B, last paragraph; Sec.
+ *     III-C).  T is represented by a lattice of sample points per facet.
+ *   - Visual angle (Eq. 1) with oblique foreshortening (Eq. 2):
+ *     V = 2 arctan(S_alpha / 2D), S_alpha = (alpha / 90 deg) S.
+ *   - Field of view (Sec. III-B): viewpoints outside the FOV wedge around the
+ *     target normal are obstructed.
+ *
+ * Readings taken where the paper is silent (all listed in the design notes):
+ *   - S is the largest target dimension; D is the distance from the viewpoint
+ *     to the target centre, floored at the near point d0; alpha is the angle
+ *     between the line of sight and the target plane, measured in the
+ *     meridian plane (h = |Delta . n|, rho = |Delta - (Delta . n) n|).
+ *   - c = V / V0 with V0 = 2 arctan(S / 2 d0), the largest visual angle.
+ *   - Cube targets: n is the axis of largest |Delta_k|; only faces facing the
+ *     viewpoint (strictly) carry live samples.
+ *   - FULL mode is the paper's complete-visibility rule; FRACTION mode scales
+ *     the colour by the visible fraction of live samples (an extension).
+ *   - Linear colour bins: bin = min(B-1, floor(c B)); the log scale is a test
+ *     aid that spreads visual angles between mu and V0 over the bins.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { VO_SEGMENT = 0, VO_BILLBOARD = 1, VO_CUBE = 2 };
+enum { VO_FULL = 0, VO_FRACTION = 1 };
+enum { VO_BIN_LINEAR = 0, VO_BIN_LOG = 1 };
+
+typedef struct {
+    int kind;
+    int normal_axis;
+    int normal_sign;
+    int su, sv;
+    double center[3];
+    double size[2];
+} vo_target;
+
+typedef struct {
+    double origin[3];
+    double extent[3];
+    int64_t n[3];
+} vo_grid;
+
+typedef struct {
+    double mu_arcmin;
+    double d0;
+    double fov_deg;
+    int n_bins;
+    int bin_scale;
+    int mode;
+} vo_params;
+
+#define VO_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------ exactness -- */
+
+/* x as an integer count of 2^-8 quanta; -1 if x is not such a multiple or
+ * is out of range. */
+static int to_quanta(double x, int64_t *out)
+{
+    double y = x * 256.0;
+    if (!(fabs(y) < 4194304.0) || y != floor(y))
+        return -1;
+    *out = (int64_t)y;
+    return 0;
+}
+
+/* ------------------------------------------ point-to-point visibility ---- */
+
+/* Does the closed segment [q, s] meet the closed box [lo, hi]?  All values in
+ * quanta.  The segment is q + t (s - q), t in [0, 1].  Along each axis the
+ * box admits an interval of t; the segment meets the box iff the largest
+ * lower end is not above the smallest upper end (together with [0, 1]).
+ * Every interval end is a fraction num/den with den > 0, so each comparison
+ * is done by cross-multiplication, exactly. */
+static int seg_meets_box(int dim, const int64_t *q, const int64_t *s,
+                         const int64_t *lo, const int64_t *hi)
+{
+    int64_t lnum[3], unum[3], den[3];
+    int m = 0;
+    for (int k = 0; k < dim; ++k) {
+        int64_t d = s[k] - q[k];
+        if (d == 0) {
+            if (q[k] < lo[k] || q[k] > hi[k])
+                return 0;
+            continue;
+        }
+        int64_t a, b, e;
+        if (d > 0) {
+            a = lo[k] - q[k];
+            b = hi[k] - q[k];
+            e = d;
+        } else {
+            a = q[k] - hi[k];
+            b = q[k] - lo[k];
+            e = -d;
+        }
+        /* lower end a/e must not exceed 1; upper end b/e must not be below 0 */
+        if (a > e || b < 0)
+            return 0;
+        lnum[m] = a;
+        unum[m] = b;
+        den[m] = e;
+        ++m;
+    }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j)
+            if (i != j && lnum[i] * den[j] > unum[j] * den[i])
+                return 0;
+    return 1;
+}
+
+/* Public wrapper on doubles (inputs must be multiples of 2^-8).
+ * Returns 1 (meets), 0 (misses), -1 (invalid input). */
+int vo_segment_meets_box(int dim, const double *q, const double *s,
+                         const double *lo, const double *hi)
+{
+    int64_t Q[3] = {0, 0, 0}, S[3] = {0, 0, 0}, L[3] = {0, 0, 0}, H[3] = {0, 0, 0};
+    for (int k = 0; k < dim; ++k) {
+        if (to_quanta(q[k], &Q[k]) || to_quanta(s[k], &S[k]) ||
+            to_quanta(lo[k], &L[k]) || to_quanta(hi[k], &H[k]))
+            return -1;
+        if (L[k] > H[k])
+            return -1;
+    }
+    return seg_meets_box(dim, Q, S, L, H);
+}
+
+/* --------------------------------------------------------- target side -- */
+
+static double target_size(const vo_target *t)
+{
+    if (t->kind == VO_BILLBOARD)
+        return t->size[0] > t->size[1] ? t->size[0] : t->size[1];
+    return t->size[0];
+}
+
+/* Live samples of T seen from q: facet-lattice cell centres
+ * (k + 1/2) / N along each facet direction.  Segment: N_u points along the
+ * axis orthogonal to the normal.  Billboard: N_u (horizontal) x N_v
+ * (vertical) on the plane orthogonal to the normal axis.  Cube: N_u x N_v per
+ * face, faces in the order (-x, +x, -y, +y, -z, +z), a face being live only
+ * when q lies strictly on its outer side.  Returns N(q). */
+int vo_live_samples(const vo_target *t, const double *q, double *out)
+{
+    int n = 0;
+    const double *c = t->center;
+    if (t->kind == VO_SEGMENT || t->kind == VO_BILLBOARD) {
+        int a = t->normal_axis;
+        int w = 1 - a;
+        double W = t->size[0];
+        double H = t->kind == VO_BILLBOARD ? t->size[1] : 0.0;
+        int nv = t->kind == VO_BILLBOARD ? t->sv : 1;
+        for (int iv = 0; iv < nv; ++iv)
+            for (int iu = 0; iu < t->su; ++iu) {
+                double p[3];
+                p[a] = c[a];
+                p[w] = c[w] - W / 2.0 + (iu + 0.5) * (W / t->su);
+                p[2] = t->kind == VO_BILLBOARD ? c[2] - H / 2.0 + (iv + 0.5) * (H / nv) : 0.0;
+                if (out) {
+                    out[3 * n + 0] = p[0];
+                    out[3 * n + 1] = p[1];
+                    out[3 * n + 2] = p[2];
+                }
+                ++n;
+            }
+        return n;
+    }
+    /* cube */
+    double E = t->size[0];
+    for (int f = 0; f < 6; ++f) {
+        int k = f / 2;
+        int sgn = (f % 2) ? 1 : -1;
+        double plane = c[k] + sgn * E / 2.0;
+        if (!(sgn * (q[k] - plane) > 0.0))
+            continue;
+        int ua = (k == 0) ? 1 : 0;
+        int vb = (k == 2) ? 1 : 2;
+        for (int iv = 0; iv < t->sv; ++iv)
+            for (int iu = 0; iu < t->su; ++iu) {
+                double p[3];
+                p[k] = plane;
+                p[ua] = c[ua] - E / 2.0 + (iu + 0.5) * (E / t->su);
+                p[vb] = c[vb] - E / 2.0 + (iv + 0.5) * (E / t->sv);
+                if (out) {
+                    out[3 * n + 0] = p[0];
+                    out[3 * n + 1] = p[1];
+                    out[3 * n + 2] = p[2];
+                }
+                ++n;
+            }
+    }
+    return n;
+}
+
+/* ----------------------------------------------------------- measure ----- */
+
+/* Visual angle of T from q (Eq. 1 with the oblique size of Eq. 2).
+ * out = {D, alpha (rad), V (rad), V0 (rad)}. */
+void vo_measure(const vo_target *t, const vo_params *p, const double *q, double *out)
+{
+    double dl[3];
+    for (int k = 0; k < 3; ++k)
+        dl[k] = q[k] - t->center[k];
+    if (t->kind == VO_SEGMENT)
+        dl[2] = 0.0; /* the 2-D plane */
+    int nax;
+    if (t->kind == VO_CUBE) {
+        nax = 0;
+        for (int k = 1; k < 3; ++k)
+            if (fabs(dl[k]) > fabs(dl[nax]))
+                nax = k;
+    } else {
+        nax = t->normal_axis;
+    }
+    double h = fabs(dl[nax]);
+    double r2 = 0.0;
+    for (int k = 0; k < 3; ++k)
+        if (k != nax)
+            r2 += dl[k] * dl[k];
+    double rho = sqrt(r2);
+    double D = sqrt(r2 + h * h);
+    double alpha = atan2(h, rho);                 /* 90 deg facing, 0 edge-on */
+    double S = target_size(t);
+    double s_alpha = (alpha / (VO_PI / 2.0)) * S; /* Eq. 2 */
+    double Dn = D > p->d0 ? D : p->d0;            /* no closer than the near point */
+    double V = 2.0 * atan(s_alpha / (2.0 * Dn));  /* Eq. 1 */
+    double V0 = 2.0 * atan(S / (2.0 * p->d0));
+    out[0] = D;
+    out[1] = alpha;
+    out[2] = V;
+    out[3] = V0;
+}
+
+/* ----------------------------------------------------------- FOV --------- */
+
+/* Is q inside the field of view?  The wedge has its apex at the target
+ * centre and is symmetric about the target normal n (viewer-at-target
+ * symmetry, Sec. III-A): angle(q - m, n) <= FOV / 2, closed.  The test
+ * compares (Delta.n)^2 with cos^2(FOV/2) |Delta|^2; cos^2 is an exact rational
+ * for the table's half-angles 30/60/120/150 degrees. */
+int vo_in_fov(const vo_target *t, const vo_params *p, const double *q)
+{
+    double half = p->fov_deg / 2.0;
+    if (half >= 180.0)
+        return 1;
+    double dl[3], d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        dl[k] = (t->kind == VO_SEGMENT && k == 2) ? 0.0 : q[k] - t->center[k];
+        d2 += dl[k] * dl[k];
+    }
+    double dn = t->normal_sign * dl[t->normal_axis];
+    if (half == 90.0)
+        return dn >= 0.0;
+    double c2;
+    if (half == 30.0 || half == 150.0)
+        c2 = 0.75;
+    else if (half == 60.0 || half == 120.0)
+        c2 = 0.25;
+    else {
+        double cs = cos(half * VO_PI / 180.0);
+        c2 = cs * cs;
+    }
+    if (half < 90.0)
+        return dn >= 0.0 && dn * dn >= c2 * d2;
+    return dn >= 0.0 || dn * dn <= c2 * d2;
+}
+
+/* ----------------------------------------------------------- colour ------ */
+
+/* Colour in the bin's scale and the bin index. */
+static void to_bin(const vo_params *p, double c, double V0, double *cb, uint8_t *bin)
+{
+    double v;
+    if (p->bin_scale == VO_BIN_LOG) {
+        double mu = p->mu_arcmin * VO_PI / (180.0 * 60.0);
+        double Veff = c * V0;
+        if (Veff <= mu)
+            v = 0.0;
+        else {
+            v = log(Veff / mu) / log(V0 / mu);
+            if (v > 1.0)
+                v = 1.0;
+        }
+    } else {
+        v = c;
+    }
+    double f = floor(v * p->n_bins);
+    int b = (int)f;
+    if (b > p->n_bins - 1)
+        b = p->n_bins - 1;
+    if (b < 0)
+        b = 0;
+    *cb = v;
+    *bin = (uint8_t)b;
+}
+
+/* ----------------------------------------------------------- the map ----- */
+
+typedef struct {
+    int dim;
+    int64_t nbox;
+    int64_t *blo, *bhi; /* quanta, [box][3] */
+    const vo_target *t;
+    const vo_grid *g;
+    const vo_params *p;
+    const int64_t *vp;
+    int64_t nvp;
+    uint16_t *count, *nlive;
+    uint8_t *infov, *bin;
+    double *c, *cb;
+    int64_t first, last;
+} vo_job;
+
+static void eval_range(vo_job *J)
+{
+    const vo_target *t = J->t;
+    const vo_grid *g = J->g;
+    const vo_params *p = J->p;
+    int maxs = 6 * t->su * (t->sv > 0 ? t->sv : 1);
+    double *smp = (double *)malloc(sizeof(double) * 3 * (size_t)maxs);
+    int64_t *sq = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)maxs);
+    for (int64_t v = J->first; v < J->last; ++v) {
+        int64_t idx = J->vp[v];
+        int64_t i = idx % g->n[0];
+        int64_t j = (idx / g->n[0]) % g->n[1];
+        int64_t k = idx / (g->n[0] * g->n[1]);
+        int64_t ii[3] = {i, j, k};
+        double q[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < J->dim; ++a)
+            q[a] = g->origin[a] + (double)(2 * ii[a] + 1) * (g->extent[a] / (2.0 * (double)g->n[a]));
+        int n = vo_live_samples(t, q, smp);
+        int inf = vo_in_fov(t, p, q);
+        double m[4];
+        vo_measure(t, p, q, m);
+        double craw = m[2] / m[3];
+        int vis = 0;
+        if (inf && n > 0) {
+            int64_t Q[3] = {0, 0, 0};
+            for (int a = 0; a < J->dim; ++a)
+                to_quanta(q[a], &Q[a]);
+            for (int s = 0; s < n; ++s)
+                for (int a = 0; a < 3; ++a)
+                    sq[3 * s + a] = 0;
+            for (int s = 0; s < n; ++s)
+                for (int a = 0; a < J->dim; ++a)
+                    to_quanta(smp[3 * s + a], &sq[3 * s + a]);
+            for (int s = 0; s < n; ++s) {
+                int blocked = 0;
+                for (int64_t b = 0; b < J->nbox && !blocked; ++b)
+                    blocked = seg_meets_box(J->dim, Q, &sq[3 * s], &J->blo[3 * b], &J->bhi[3 * b]);
+                vis += !blocked;
+            }
+        }
+        int cnt;
+        double col;
+        if (!inf || n == 0) {
+            cnt = 0;
+            col = 0.0;
+        } else if (p->mode == VO_FRACTION) {
+            cnt = vis;
+            col = ((double)vis / (double)n) * craw;
+        } else {
+            cnt = (vis == n) ? n : 0;
+            col = (vis == n) ? craw : 0.0;
+        }
+        double cbv;
+        uint8_t bn;
+        to_bin(p, col, m[3], &cbv, &bn);
+        if (J->count) J->count[v] = (uint16_t)cnt;
+        if (J->nlive) J->nlive[v] = (uint16_t)n;
+        if (J->infov) J->infov[v] = (uint8_t)inf;
+        if (J->c) J->c[v] = col;
+        if (J->cb) J->cb[v] = cbv;
+        if (J->bin) J->bin[v] = bn;
+    }
+    free(smp);
+    free(sq);
+}
+
+static void *eval_thread(void *arg)
+{
+    eval_range((vo_job *)arg);
+    return NULL;
+}
+
+/* Checks that every coordinate the map touches is a multiple of 2^-8. */
+static int check_query(int dim, const vo_target *t, const vo_grid *g, const vo_params *p)
+{
+    int64_t dummy;
+    if (dim != 2 && dim != 3) return -1;
+    if (p->n_bins < 2 || p->n_bins > 256) return -1;
+    if (t->su <= 0 || t->sv <= 0) return -1;
+    if ((t->kind == VO_SEGMENT) != (dim == 2)) return -1;
+    if (t->kind != VO_CUBE && t->normal_axis != 0 && t->normal_axis != 1) return -1;
+    if (t->kind == VO_CUBE && p->fov_deg < 360.0) return -1;
+    if (!(p->fov_deg > 0.0 && p->fov_deg <= 360.0)) return -1;
+    if (!(p->mu_arcmin > 0.0) || !(p->d0 > 0.0)) return -1;
+    for (int a = 0; a < dim; ++a) {
+        if (g->n[a] <= 0) return -1;
+        if (to_quanta(g->origin[a], &dummy)) return -1;
+        if (to_quanta(g->extent[a] / (2.0 * (double)g->n[a]), &dummy)) return -1;
+    }
+    double q[3] = {1e300, 1e300, 1e300};
+    int maxs = 6 * t->su * t->sv;
+    double *smp = (double *)malloc(sizeof(double) * 3 * (size_t)maxs);
+    int n = vo_live_samples(t, q, smp);
+    /* a far viewpoint sees at most 3 cube faces; check all faces from both sides */
+    int bad = 0;
+    for (int s = 0; s < n; ++s)
+        for (int a = 0; a < dim; ++a)
+            if (to_quanta(smp[3 * s + a], &dummy)) bad = 1;
+    double q2[3] = {-1e300, -1e300, -1e300};
+    n = vo_live_samples(t, q2, smp);
+    for (int s = 0; s < n; ++s)
+        for (int a = 0; a < dim; ++a)
+            if (to_quanta(smp[3 * s + a], &dummy)) bad = 1;
+    free(smp);
+    return bad ? -1 : 0;
+}
+
+/* Evaluate the VCM at the listed viewpoints (linear index, x fastest).
+ * lo/hi: [3][nbox] SoA, multiples of 2^-8.  Any output pointer may be NULL.
+ * count: FRACTION mode: visible live samples; FULL mode: N(q) when all are
+ * visible, else 0; 0 outside the FOV.  c: colour; cb: colour in the bin's
+ * scale.  Returns 0, or -1 on invalid input. */
+int vo_eval(int dim, int64_t nbox, const double *lo, const double *hi,
+            const vo_target *t, const vo_grid *g, const vo_params *p,
+            const int64_t *vp, int64_t nvp, int nthreads,
+            uint16_t *count, uint16_t *nlive, uint8_t *infov,
+            double *c, double *cb, uint8_t *bin)
+{
+    if (check_query(dim, t, g, p))
+        return -1;
+    int64_t *blo = (int64_t *)calloc((size_t)(nbox > 0 ? nbox : 1) * 3, sizeof(int64_t));
+    int64_t *bhi = (int64_t *)calloc((size_t)(nbox > 0 ? nbox : 1) * 3, sizeof(int64_t));
+    for (int64_t b = 0; b < nbox; ++b)
+        for (int a = 0; a < dim; ++a) {
+            if (to_quanta(lo[a * nbox + b], &blo[3 * b + a]) ||
+                to_quanta(hi[a * nbox + b], &bhi[3 * b + a]) ||
+                blo[3 * b + a] > bhi[3 * b + a]) {
+                free(blo);
+                free(bhi);
+                return -1;
+            }
+        }
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    vo_job base = {dim, nbox, blo, bhi, t, g, p, vp, nvp, count, nlive, infov, bin, c, cb, 0, nvp};
+    if (nthreads == 1) {
+        eval_range(&base);
+    } else {
+        vo_job jobs[256];
+        pthread_t th[256];
+        for (int i = 0; i < nthreads; ++i) {
+            jobs[i] = base;
+            jobs[i].first = nvp * i / nthreads;
+            jobs[i].last = nvp * (i + 1) / nthreads;
+            pthread_create(&th[i], NULL, eval_thread, &jobs[i]);
+        }
+        for (int i = 0; i < nthreads; ++i)
+            pthread_join(th[i], NULL);
+    }
+    free(blo);
+    free(bhi);
+    return 0;
+}
