@@ -1,0 +1,206 @@
+/*
+ * vcm.h -- C-ABI of the MI355X visibility color map (VCM) library.
+ *
+ * Problem statement (Def. 2.1, target-centric form): given obstacles O and a
+ * target T, return a colour c in [0,1] for every viewpoint of a discretised
+ * d-dimensional space (d = 2 or 3).  The colour is the visual angle of T
+ * (Eq. 1, with the oblique size of Eq. 2) normalised by its largest value,
+ * and it is 0 wherever T is not completely visible (obstructed region,
+ * Def. 2.3) or outside the field of view (Sec. III-B).  The parameters follow
+ * the paper's parameter table (Table 2).
+ *
+ * Conventions for every entry point:
+ *   - Plain C types only.  Each call returns a vcm_status; on failure the
+ *     outputs are untouched and vcm_last_error() (thread-local) holds a
+ *     message.
+ *   - Coordinates are metres.  Every coordinate handed to the library (box
+ *     bounds, target centre and sizes, grid origin, and the derived sample
+ *     and viewpoint positions) must be a multiple of 2^-8 with magnitude
+ *     below 2^14; otherwise VCM_E_INVALID.  This makes float32 hold every
+ *     input and every difference exactly, which is what lets the float32 ray
+ *     test with its float64 recheck return exact visibility.
+ *   - Result buffers are device memory owned by the caller (for example
+ *     torch tensors passed by data_ptr()).  The library never frees them.
+ *   - `stream` is a hipStream_t cast to void*; NULL means the null stream.
+ *     Calls enqueue work on that stream and return without waiting, unless
+ *     stated otherwise.
+ */
+#ifndef VCM_H
+#define VCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VCM_OK = 0,
+    VCM_E_INVALID = 1,  /* bad argument; see vcm_last_error()            */
+    VCM_E_NOMEM = 2,    /* device or host allocation failed               */
+    VCM_E_DEVICE = 3,   /* a HIP call or kernel launch failed             */
+    VCM_E_AGAIN = 4,    /* admission refused for now; retry later         */
+    VCM_E_NOTFOUND = 5, /* unknown ticket                                 */
+    VCM_E_PENDING = 6,  /* request not finished yet                       */
+    VCM_E_INTERNAL = 7  /* library bug or request cancelled at shutdown   */
+} vcm_status;
+
+/* Message for the calling thread's most recent failure ("" if none). */
+const char *vcm_last_error(void);
+
+/* Library version string. */
+const char *vcm_version(void);
+
+/* ------------------------------------------------------------ obstacles --- */
+
+/* Obstacles O: closed axis-aligned boxes [lo, hi] (Def. 2.2 treats an
+ * obstacle as the set a line of sight must not cut; Def. 3.1 counts touching
+ * as blocking).  Host memory, structure of arrays: lo[k][i], hi[k][i] for
+ * axis k < dim and box i < n.  For dim == 2 the z arrays are ignored and may
+ * be NULL.  The arrays are read during the call only. */
+typedef struct {
+    int32_t dim;            /* 2 or 3                                        */
+    int64_t n;              /* number of boxes, >= 0                         */
+    const double *lo[3];
+    const double *hi[3];
+} vcm_obstacles;
+
+typedef struct {
+    double cell_size;       /* column width in metres, a power of two; 0 = automatic */
+    int32_t device;         /* HIP device ordinal                            */
+    void *stream;           /* stream for the build; NULL = null stream      */
+} vcm_index_opts;
+
+typedef struct vcm_index vcm_index;
+
+/* Build the device-resident obstacle index: a uniform grid of vertical
+ * columns over the boxes' footprints, each listing the boxes whose footprint,
+ * grown by 2^-6 m, overlaps the column, sorted by decreasing top height.
+ * It replaces the paper's disk R*-tree (Sec. III-B) and is immutable once
+ * built.  Blocks until the index is ready.  *out owns device memory until
+ * vcm_free_index. */
+vcm_status vcm_build_index(const vcm_obstacles *obstacles, const vcm_index_opts *opts,
+                           vcm_index **out);
+
+/* Release an index.  No call that uses it may be in flight. */
+vcm_status vcm_free_index(vcm_index *index);
+
+/* Size of the index on the device in bytes, and its column grid. */
+typedef struct {
+    int64_t n_boxes;
+    int64_t n_refs;        /* box references over all columns              */
+    int32_t nx, ny;        /* columns                                      */
+    double cell_size;
+    double origin[2];
+    size_t device_bytes;
+    double build_ms;       /* wall time of the build                       */
+} vcm_index_info;
+vcm_status vcm_index_get_info(const vcm_index *index, vcm_index_info *info);
+
+/* --------------------------------------------------------------- queries --- */
+
+typedef enum {
+    VCM_SEGMENT = 0,   /* 2-D line target (Sec. III uses it for exposition) */
+    VCM_BILLBOARD = 1, /* 3-D vertical rectangle                            */
+    VCM_CUBE = 2       /* 3-D axis-aligned cube                             */
+} vcm_target_kind;
+
+/* Target T.  Segment: length size[0], lying along the axis orthogonal to
+ * normal_axis (0 = x, 1 = y).  Billboard: width size[0] (horizontal, along
+ * the other horizontal axis) by height size[1] (z), in the vertical plane
+ * orthogonal to normal_axis.  Cube: edge size[0].  T is represented by the
+ * centres of a samples_u x samples_v lattice on each facet; a viewpoint sees
+ * T only if it sees every live sample (Def. 2.3).  For the cube, a face's
+ * samples are live only for viewpoints strictly outside its plane.  The
+ * paper's size S in Eq. 1 is the largest of the target's dimensions. */
+typedef struct {
+    int32_t kind;
+    int32_t normal_axis;   /* segment, billboard: 0 or 1                    */
+    int32_t normal_sign;   /* +1 or -1: orientation of the FOV wedge        */
+    int32_t samples_u;     /* 1..64                                         */
+    int32_t samples_v;     /* 1..64 (segment: 1)                            */
+    double center[3];
+    double size[2];
+} vcm_target;
+
+/* Viewpoints: cell centres of an n[0] x n[1] x n[2] lattice over the box
+ * [origin, origin + extent]; viewpoint (i, j, k) sits at
+ * origin + (2i+1, 2j+1, 2k+1) * extent / (2n) and has linear index
+ * i + n[0] (j + n[1] k).  For dim == 2, n[2] must be 1 and z is ignored. */
+typedef struct {
+    double origin[3];
+    double extent[3];
+    int32_t n[3];
+} vcm_grid;
+
+typedef enum { VCM_BRUTE = 0, VCM_PRUNED_E = 1, VCM_PRUNED_M = 2, VCM_PRUNED_T = 3 } vcm_method;
+typedef enum { VCM_FULL = 0, VCM_FRACTION = 1 } vcm_mode;
+typedef enum { VCM_BIN_LINEAR = 0, VCM_BIN_LOG = 1 } vcm_bin_scale;
+
+/* Parameters (Table 2 names and defaults where the paper gives them). */
+typedef struct {
+    double mu_arcmin;      /* angular resolution mu, arcminutes (4)          */
+    double near_d0;        /* near-point distance d0, metres (0.25)          */
+    double fov_deg;        /* field of view, (0, 360]; cube targets need 360 */
+    int32_t n_bins;        /* colour bins B, 2..256                          */
+    int32_t bin_scale;     /* vcm_bin_scale                                  */
+    int32_t method;        /* vcm_method                                     */
+    int32_t mode;          /* VCM_FULL: the paper's complete-visibility rule;
+                              VCM_FRACTION: colour scaled by the visible
+                              fraction of live samples                      */
+    int32_t theta_blocks;  /* minimum block size, in viewpoints (1)          */
+    double recheck_eps;    /* float32 slab-test margin in units of the ray
+                              parameter (2^-20); +inf rechecks every test   */
+    int32_t precision;     /* VCM_FP32_RECHECK: float32 ray tests, exact
+                              float64 recheck near the boundary, float32
+                              measure; VCM_FP64: every ray test exact in
+                              float64 and the measure in float64           */
+    int32_t reserved;
+} vcm_params;
+
+typedef enum { VCM_FP32_RECHECK = 0, VCM_FP64 = 1 } vcm_precision;
+
+typedef struct {
+    vcm_target target;
+    vcm_grid grid;
+    vcm_params params;
+} vcm_query;
+
+/* Optional counters for one call (collected only when requested). */
+typedef struct {
+    uint64_t viewpoints;     /* viewpoints in the grid                       */
+    uint64_t rays;           /* live samples summed over in-FOV viewpoints   */
+    uint64_t box_tests;      /* float32 ray/box slab tests                   */
+    uint64_t rechecks;       /* tests sent to the exact float64 predicate    */
+    uint64_t fp32_disagree;  /* with recheck_eps = +inf: float32 decisions,
+                                taken with the default margin, that differ
+                                from the exact predicate (must be 0)        */
+    uint64_t columns;        /* grid columns visited                         */
+    double kernel_ms;        /* device time of the call's kernels            */
+} vcm_stats;
+
+/* Results: caller-owned device buffers of grid.n[0]*n[1]*n[2] entries.
+ *   bin   : colour bin, min(B-1, floor(c' B)) with c' the colour in the
+ *           chosen scale (required);
+ *   c     : colour in [0, 1] (optional, may be NULL);
+ *   count : FRACTION mode: visible live samples; FULL mode: N(q) where
+ *           every live sample is visible, else 0; 0 outside the FOV
+ *           (optional, may be NULL). */
+typedef struct {
+    uint8_t *bin;
+    float *c;
+    uint16_t *count;
+} vcm_result;
+
+/* Compute one VCM.  Enqueues on `stream` and returns; the results are ready
+ * when the stream reaches this point.  If stats is non-NULL the call also
+ * gathers counters, which makes it wait for the stream before returning. */
+vcm_status vcm_compute(const vcm_index *index, const vcm_query *query,
+                       const vcm_result *result, void *stream, vcm_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VCM_H */

@@ -1,0 +1,268 @@
+"""MI355X visibility color maps: thin ctypes binding of libvcm (include/vcm.h).
+
+The functions named like the C entry points (vcm_build_index, vcm_compute,
+...) only marshal arguments: every step of the computation runs in the HIP
+kernels of libvcm.so.  torch supplies device memory and streams.  There is no
+fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import scenes
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvcm.so")
+
+VCM_OK, VCM_E_INVALID, VCM_E_NOMEM, VCM_E_DEVICE, VCM_E_AGAIN, VCM_E_NOTFOUND, \
+    VCM_E_PENDING, VCM_E_INTERNAL = range(8)
+STATUS_NAMES = {0: "VCM_OK", 1: "VCM_E_INVALID", 2: "VCM_E_NOMEM", 3: "VCM_E_DEVICE",
+                4: "VCM_E_AGAIN", 5: "VCM_E_NOTFOUND", 6: "VCM_E_PENDING", 7: "VCM_E_INTERNAL"}
+VCM_FP32_RECHECK, VCM_FP64 = 0, 1
+
+# Every symbol include/vcm.h declares.
+EXPORTS = ("vcm_last_error", "vcm_version", "vcm_build_index", "vcm_free_index",
+           "vcm_index_get_info", "vcm_compute")
+
+
+class VcmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class vcm_obstacles(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("lo", ctypes.c_void_p * 3), ("hi", ctypes.c_void_p * 3)]
+
+
+class vcm_index_opts(ctypes.Structure):
+    _fields_ = [("cell_size", ctypes.c_double), ("device", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class vcm_index_info(ctypes.Structure):
+    _fields_ = [("n_boxes", ctypes.c_int64), ("n_refs", ctypes.c_int64),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("cell_size", ctypes.c_double),
+                ("origin", ctypes.c_double * 2), ("device_bytes", ctypes.c_size_t),
+                ("build_ms", ctypes.c_double)]
+
+
+class vcm_target(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("normal_axis", ctypes.c_int32),
+                ("normal_sign", ctypes.c_int32), ("samples_u", ctypes.c_int32),
+                ("samples_v", ctypes.c_int32), ("center", ctypes.c_double * 3),
+                ("size", ctypes.c_double * 2)]
+
+
+class vcm_grid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("extent", ctypes.c_double * 3),
+                ("n", ctypes.c_int32 * 3)]
+
+
+class vcm_params(ctypes.Structure):
+    _fields_ = [("mu_arcmin", ctypes.c_double), ("near_d0", ctypes.c_double),
+                ("fov_deg", ctypes.c_double), ("n_bins", ctypes.c_int32),
+                ("bin_scale", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("theta_blocks", ctypes.c_int32),
+                ("recheck_eps", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class vcm_query(ctypes.Structure):
+    _fields_ = [("target", vcm_target), ("grid", vcm_grid), ("params", vcm_params)]
+
+
+class vcm_stats(ctypes.Structure):
+    _fields_ = [("viewpoints", ctypes.c_uint64), ("rays", ctypes.c_uint64),
+                ("box_tests", ctypes.c_uint64), ("rechecks", ctypes.c_uint64),
+                ("fp32_disagree", ctypes.c_uint64), ("columns", ctypes.c_uint64),
+                ("kernel_ms", ctypes.c_double)]
+
+
+class vcm_result(ctypes.Structure):
+    _fields_ = [("bin", ctypes.c_void_p), ("c", ctypes.c_void_p), ("count", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libvcm.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime libvcm links against)
+    except ImportError:
+        pass
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(path)
+    L.vcm_last_error.restype = ctypes.c_char_p
+    L.vcm_version.restype = ctypes.c_char_p
+    L.vcm_build_index.argtypes = [ctypes.POINTER(vcm_obstacles), ctypes.POINTER(vcm_index_opts),
+                                  ctypes.POINTER(ctypes.c_void_p)]
+    L.vcm_free_index.argtypes = [ctypes.c_void_p]
+    L.vcm_index_get_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_index_info)]
+    L.vcm_compute.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_query),
+                              ctypes.POINTER(vcm_result), ctypes.c_void_p,
+                              ctypes.POINTER(vcm_stats)]
+    for name in ("vcm_build_index", "vcm_free_index", "vcm_index_get_info", "vcm_compute"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != VCM_OK:
+        raise VcmError(status, vcm_last_error())
+
+
+def vcm_last_error() -> str:
+    return load_library().vcm_last_error().decode()
+
+
+def vcm_version() -> str:
+    return load_library().vcm_version().decode()
+
+
+# ------------------------------------------------------------ conversions ---
+
+def make_target(t: scenes.Target) -> vcm_target:
+    T = vcm_target()
+    T.kind, T.normal_axis, T.normal_sign = int(t.kind), int(t.normal_axis), int(t.normal_sign)
+    T.samples_u, T.samples_v = int(t.samples_u), int(t.samples_v)
+    for k in range(3):
+        T.center[k] = float(t.center[k])
+    T.size[0], T.size[1] = float(t.size[0]), float(t.size[1])
+    return T
+
+
+def make_query(q: scenes.Query, precision: int = VCM_FP32_RECHECK) -> vcm_query:
+    Q = vcm_query()
+    Q.target = make_target(q.target)
+    for k in range(3):
+        Q.grid.origin[k] = float(q.grid.origin[k])
+        Q.grid.extent[k] = float(q.grid.extent[k])
+        Q.grid.n[k] = int(q.grid.n[k])
+    p = q.params
+    P = Q.params
+    P.mu_arcmin, P.near_d0, P.fov_deg = float(p.mu_arcmin), float(p.near_d0), float(p.fov_deg)
+    P.n_bins, P.bin_scale, P.method = int(p.n_bins), int(p.bin_scale), int(p.method)
+    P.mode, P.theta_blocks = int(p.mode), int(p.theta_blocks)
+    P.recheck_eps = float(p.recheck_eps)
+    P.precision = int(precision)
+    return Q
+
+
+# ------------------------------------------------------------ entry points ---
+
+class Index:
+    """Owns a vcm_index handle."""
+
+    def __init__(self, handle: int, dim: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.dim = dim
+
+    def info(self) -> Dict[str, float]:
+        return vcm_index_get_info(self)
+
+    def free(self):
+        if self.handle:
+            vcm_free_index(self)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def vcm_build_index(scene: scenes.Scene, cell_size: float = 0.0, device: int = 0,
+                    stream: Optional[int] = None) -> Index:
+    L = load_library()
+    lo = np.ascontiguousarray(scene.lo, dtype=np.float64)
+    hi = np.ascontiguousarray(scene.hi, dtype=np.float64)
+    O = vcm_obstacles()
+    O.dim = int(scene.dim)
+    O.n = int(lo.shape[1])
+    for k in range(3):
+        O.lo[k] = lo[k].ctypes.data if O.n else None
+        O.hi[k] = hi[k].ctypes.data if O.n else None
+    opts = vcm_index_opts(float(cell_size), int(device), stream)
+    h = ctypes.c_void_p()
+    _check(L.vcm_build_index(ctypes.byref(O), ctypes.byref(opts), ctypes.byref(h)))
+    return Index(h.value, int(scene.dim))
+
+
+def vcm_free_index(index: Index):
+    _check(load_library().vcm_free_index(index.handle))
+    index.handle = ctypes.c_void_p()
+
+
+def vcm_index_get_info(index: Index) -> Dict[str, float]:
+    info = vcm_index_info()
+    _check(load_library().vcm_index_get_info(index.handle, ctypes.byref(info)))
+    return {"n_boxes": info.n_boxes, "n_refs": info.n_refs, "nx": info.nx, "ny": info.ny,
+            "cell_size": info.cell_size, "origin": (info.origin[0], info.origin[1]),
+            "device_bytes": info.device_bytes, "build_ms": info.build_ms}
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def vcm_compute(index: Index, query: scenes.Query, bin_out, c_out=None, count_out=None,
+                stream=None, stats: bool = False, precision: int = VCM_FP32_RECHECK):
+    """Enqueue one VCM on `stream` (default: torch's current stream).
+
+    bin_out (uint8), c_out (float32), count_out (int16 storage of uint16) are
+    torch tensors on the device with one entry per viewpoint."""
+    L = load_library()
+    Q = make_query(query, precision)
+    n = query.grid.count
+    for t, name in ((bin_out, "bin"), (c_out, "c"), (count_out, "count")):
+        if t is not None:
+            if not t.is_cuda or t.numel() < n or not t.is_contiguous():
+                raise ValueError(f"{name}: need a contiguous device tensor of >= {n} entries")
+    R = vcm_result(bin_out.data_ptr(), c_out.data_ptr() if c_out is not None else None,
+                   count_out.data_ptr() if count_out is not None else None)
+    st = vcm_stats()
+    _check(L.vcm_compute(index.handle, ctypes.byref(Q), ctypes.byref(R), _stream_ptr(stream),
+                         ctypes.byref(st) if stats else None))
+    if stats:
+        return {f: getattr(st, f) for f, _ in vcm_stats._fields_}
+    return None
+
+
+def alloc_result(n: int, device="cuda"):
+    import torch
+    return (torch.empty(n, dtype=torch.uint8, device=device),
+            torch.empty(n, dtype=torch.float32, device=device),
+            torch.empty(n, dtype=torch.int16, device=device))
+
+
+def compute_map(index: Index, query: scenes.Query, stats: bool = False,
+                precision: int = VCM_FP32_RECHECK):
+    """Convenience: allocate, compute, synchronise, return numpy arrays."""
+    import torch
+    n = query.grid.count
+    b, c, cnt = alloc_result(n)
+    st = vcm_compute(index, query, b, c, cnt, stats=stats, precision=precision)
+    torch.cuda.synchronize()
+    out = {"bin": b.cpu().numpy(), "c": c.cpu().numpy(),
+           "count": cnt.cpu().numpy().view(np.uint16)}
+    if stats:
+        out["stats"] = st
+    return out

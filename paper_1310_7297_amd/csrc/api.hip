@@ -1,0 +1,318 @@
+// C-ABI entry points: argument validation, ownership, launches.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vcm_internal.h"
+
+struct vcm_index {
+    vcm::Index impl;
+};
+
+namespace vcm {
+
+static thread_local std::string g_err;
+
+vcm_status set_error(vcm_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+void clear_error() { g_err.clear(); }
+
+namespace {
+
+constexpr double kLimit = 16384.0;  // |coordinate| < 2^14
+
+bool dyadic(double x) {
+    const double y = x * 256.0;
+    return std::isfinite(y) && std::fabs(x) < kLimit && y == std::floor(y);
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+double deg2rad(double d) { return d * M_PI / 180.0; }
+
+}  // namespace
+
+vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, GridDesc *g,
+                         ParamDesc *p) {
+    const vcm_target &T = q.target;
+    const vcm_grid &G = q.grid;
+    const vcm_params &P = q.params;
+    const int dim = ix.dim;
+    // ---- target
+    if (T.kind != VCM_SEGMENT && T.kind != VCM_BILLBOARD && T.kind != VCM_CUBE)
+        return set_error(VCM_E_INVALID, "unknown target kind");
+    if ((T.kind == VCM_SEGMENT) != (dim == 2))
+        return set_error(VCM_E_INVALID, "segment targets need a 2-D index, others a 3-D index");
+    if (T.samples_u < 1 || T.samples_u > 64 || T.samples_v < 1 || T.samples_v > 64)
+        return set_error(VCM_E_INVALID, "samples_u and samples_v must be in [1, 64]");
+    if (T.kind == VCM_SEGMENT && T.samples_v != 1)
+        return set_error(VCM_E_INVALID, "a segment has samples_v == 1");
+    if (T.kind != VCM_CUBE && T.normal_axis != 0 && T.normal_axis != 1)
+        return set_error(VCM_E_INVALID, "normal_axis must be 0 or 1");
+    if (T.normal_sign != 1 && T.normal_sign != -1)
+        return set_error(VCM_E_INVALID, "normal_sign must be +1 or -1");
+    const int per_facet = T.samples_u * T.samples_v;
+    const int max_live = per_facet * (T.kind == VCM_CUBE ? 3 : 1);
+    if (max_live > kMaxSamples)
+        return set_error(VCM_E_INVALID, "at most 384 live samples per viewpoint");
+    if (!(T.size[0] > 0) || (T.kind == VCM_BILLBOARD && !(T.size[1] > 0)))
+        return set_error(VCM_E_INVALID, "target sizes must be positive");
+    for (int k = 0; k < dim; ++k)
+        if (!dyadic(T.center[k])) return set_error(VCM_E_INVALID, "target centre off the 2^-8 lattice");
+    double half[3] = {0, 0, 0};
+    double su_len = T.size[0], sv_len = 0;
+    if (T.kind == VCM_CUBE) {
+        half[0] = half[1] = half[2] = T.size[0] / 2;
+        sv_len = T.size[0];
+    } else {
+        half[1 - T.normal_axis] = T.size[0] / 2;
+        if (T.kind == VCM_BILLBOARD) {
+            half[2] = T.size[1] / 2;
+            sv_len = T.size[1];
+        }
+    }
+    const double hu = su_len / (2.0 * T.samples_u);
+    const double hv = T.kind == VCM_SEGMENT ? 0.0 : sv_len / (2.0 * T.samples_v);
+    for (int k = 0; k < 3; ++k)
+        if (!dyadic(T.center[k] - half[k]) || !dyadic(T.center[k] + half[k]))
+            return set_error(VCM_E_INVALID, "target extent off the 2^-8 lattice");
+    for (int i = 0; i < T.samples_u; ++i)
+        if (!dyadic((2 * i + 1 - T.samples_u) * hu) || !dyadic(T.center[0] + (2 * i + 1 - T.samples_u) * hu) ||
+            !dyadic(T.center[1] + (2 * i + 1 - T.samples_u) * hu))
+            return set_error(VCM_E_INVALID, "sample lattice off the 2^-8 lattice (size / samples_u)");
+    for (int i = 0; i < T.samples_v; ++i)
+        if (!dyadic((2 * i + 1 - T.samples_v) * hv) || !dyadic(T.center[2] + (2 * i + 1 - T.samples_v) * hv) ||
+            !dyadic(T.center[1] + (2 * i + 1 - T.samples_v) * hv))
+            return set_error(VCM_E_INVALID, "sample lattice off the 2^-8 lattice (size / samples_v)");
+    const double S = T.kind == VCM_BILLBOARD ? std::max(T.size[0], T.size[1]) : T.size[0];
+    // ---- grid
+    int64_t count = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (G.n[k] < 1) return set_error(VCM_E_INVALID, "grid dimensions must be >= 1");
+        count *= G.n[k];
+    }
+    if (dim == 2 && G.n[2] != 1) return set_error(VCM_E_INVALID, "2-D grids have n[2] == 1");
+    double h2[3] = {0, 0, 0};
+    for (int k = 0; k < dim; ++k) {
+        if (!(G.extent[k] >= 0)) return set_error(VCM_E_INVALID, "grid extent must be >= 0");
+        h2[k] = G.extent[k] / (2.0 * G.n[k]);
+        if (!dyadic(G.origin[k]) || !dyadic(h2[k]) || !dyadic(G.origin[k] + G.extent[k]))
+            return set_error(VCM_E_INVALID,
+                             "viewpoints off the 2^-8 lattice (origin, extent / (2 n)) or beyond 2^14");
+    }
+    if (count >= (int64_t(1) << 40)) return set_error(VCM_E_INVALID, "grid too large");
+    // ---- parameters
+    if (!(P.mu_arcmin > 0)) return set_error(VCM_E_INVALID, "mu_arcmin must be > 0");
+    if (!(P.near_d0 > 0)) return set_error(VCM_E_INVALID, "near_d0 must be > 0");
+    if (!(P.fov_deg > 0 && P.fov_deg <= 360)) return set_error(VCM_E_INVALID, "fov_deg must be in (0, 360]");
+    if (T.kind == VCM_CUBE && P.fov_deg < 360)
+        return set_error(VCM_E_INVALID, "a cube has no normal: use fov_deg = 360");
+    if (P.n_bins < 2 || P.n_bins > 256) return set_error(VCM_E_INVALID, "n_bins must be in [2, 256]");
+    if (P.bin_scale != VCM_BIN_LINEAR && P.bin_scale != VCM_BIN_LOG)
+        return set_error(VCM_E_INVALID, "unknown bin_scale");
+    if (P.mode != VCM_FULL && P.mode != VCM_FRACTION) return set_error(VCM_E_INVALID, "unknown mode");
+    if (P.method != VCM_BRUTE)
+        return set_error(VCM_E_INVALID, "method not available in vcm_compute of this build");
+    if (P.theta_blocks < 1) return set_error(VCM_E_INVALID, "theta_blocks must be >= 1");
+    if (!(P.recheck_eps >= 0)) return set_error(VCM_E_INVALID, "recheck_eps must be >= 0");
+    if (P.precision != VCM_FP32_RECHECK && P.precision != VCM_FP64)
+        return set_error(VCM_E_INVALID, "unknown precision");
+    const double mu = deg2rad(P.mu_arcmin / 60.0);
+    const double V0 = 2.0 * std::atan(S / (2.0 * P.near_d0));
+    if (!(V0 > mu)) return set_error(VCM_E_INVALID, "target below the angular resolution at the near point");
+
+    *t = TargetDesc{};
+    t->kind = T.kind;
+    t->nax = T.kind == VCM_CUBE ? 0 : T.normal_axis;
+    t->nsign = T.normal_sign;
+    t->su = T.samples_u;
+    t->sv = T.samples_v;
+    t->per_facet = per_facet;
+    for (int k = 0; k < 3; ++k) {
+        t->c[k] = (k < dim) ? (float)T.center[k] : 0.0f;
+        t->half[k] = (float)half[k];
+    }
+    t->hu = (float)hu;
+    t->hv = (float)hv;
+    t->S = (float)S;
+
+    *g = GridDesc{};
+    for (int k = 0; k < 3; ++k) {
+        g->o[k] = (k < dim) ? (float)G.origin[k] : 0.0f;
+        g->h2[k] = (float)h2[k];
+        g->n[k] = G.n[k];
+    }
+    g->count = count;
+
+    *p = ParamDesc{};
+    const double half_fov = P.fov_deg / 2.0;
+    if (half_fov >= 180.0) {
+        p->fov_kind = kFovAll;
+    } else if (half_fov == 90.0) {
+        p->fov_kind = kFovHalf;
+    } else {
+        p->fov_kind = half_fov < 90.0 ? kFovNarrow : kFovWide;
+        if (half_fov == 30.0 || half_fov == 150.0)
+            p->fov_c2 = 0.75;
+        else if (half_fov == 60.0 || half_fov == 120.0)
+            p->fov_c2 = 0.25;
+        else {
+            const double cs = std::cos(deg2rad(half_fov));
+            p->fov_c2 = cs * cs;
+        }
+    }
+    p->n_bins = P.n_bins;
+    p->bin_scale = P.bin_scale;
+    p->mode = P.mode;
+    p->d0 = (float)P.near_d0;
+    p->V0 = (float)V0;
+    p->inv_V0 = (float)(1.0 / V0);
+    p->mu = (float)mu;
+    p->inv_log_V0_mu = (float)(1.0 / std::log(V0 / mu));
+    p->recheck_all = std::isinf(P.recheck_eps) ? 1 : 0;
+    p->eps = std::isinf(P.recheck_eps) ? 0x1p-20f : (float)P.recheck_eps;
+    p->fp64 = P.precision == VCM_FP64 ? 1 : 0;
+    return VCM_OK;
+}
+
+}  // namespace vcm
+
+using namespace vcm;
+
+#define TRY_HIP(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return set_error(e_ == hipErrorOutOfMemory ? VCM_E_NOMEM : VCM_E_DEVICE,      \
+                             std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+extern "C" {
+
+const char *vcm_last_error(void) { return g_err.c_str(); }
+
+const char *vcm_version(void) { return "vcm-mi355x 0.1 (gfx950)"; }
+
+vcm_status vcm_build_index(const vcm_obstacles *obs, const vcm_index_opts *opts, vcm_index **out) {
+    clear_error();
+    if (!obs || !out) return set_error(VCM_E_INVALID, "null argument");
+    if (obs->dim != 2 && obs->dim != 3) return set_error(VCM_E_INVALID, "dim must be 2 or 3");
+    if (obs->n < 0) return set_error(VCM_E_INVALID, "negative box count");
+    if (obs->n >= (int64_t(1) << 26)) return set_error(VCM_E_INVALID, "too many boxes");
+    const int64_t n = obs->n;
+    for (int k = 0; k < obs->dim; ++k)
+        if (n > 0 && (!obs->lo[k] || !obs->hi[k])) return set_error(VCM_E_INVALID, "null box array");
+    std::vector<float> lo(3 * std::max<int64_t>(n, 1), 0.0f), hi(3 * std::max<int64_t>(n, 1), 0.0f);
+    for (int k = 0; k < obs->dim; ++k)
+        for (int64_t i = 0; i < n; ++i) {
+            const double a = obs->lo[k][i], b = obs->hi[k][i];
+            if (!dyadic(a) || !dyadic(b))
+                return set_error(VCM_E_INVALID, "box coordinate off the 2^-8 lattice or beyond 2^14 (box " +
+                                                    std::to_string(i) + ")");
+            if (a > b) return set_error(VCM_E_INVALID, "box with lo > hi (box " + std::to_string(i) + ")");
+            lo[k * n + i] = (float)a;
+            hi[k * n + i] = (float)b;
+        }
+    const int device = opts ? opts->device : 0;
+    hipStream_t stream = opts ? (hipStream_t)opts->stream : nullptr;
+    const double cs = opts ? opts->cell_size : 0.0;
+    DeviceGuard guard(device);
+    vcm_index *h = new (std::nothrow) vcm_index;
+    if (!h) return set_error(VCM_E_NOMEM, "host allocation failed");
+    h->impl.device = device;
+    h->impl.dim = obs->dim;
+    vcm_status st = build_index_device(&h->impl, lo.data(), hi.data(), n, cs, stream);
+    if (st != VCM_OK) {
+        if (h->impl.d_col_start) hipFree(h->impl.d_col_start);
+        if (h->impl.d_recs) hipFree(h->impl.d_recs);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return VCM_OK;
+}
+
+vcm_status vcm_free_index(vcm_index *index) {
+    clear_error();
+    if (!index) return VCM_OK;
+    DeviceGuard guard(index->impl.device);
+    if (index->impl.d_col_start) hipFree(index->impl.d_col_start);
+    if (index->impl.d_recs) hipFree(index->impl.d_recs);
+    delete index;
+    return VCM_OK;
+}
+
+vcm_status vcm_index_get_info(const vcm_index *index, vcm_index_info *info) {
+    clear_error();
+    if (!index || !info) return set_error(VCM_E_INVALID, "null argument");
+    const Index &ix = index->impl;
+    info->n_boxes = ix.n_boxes;
+    info->n_refs = ix.n_refs;
+    info->nx = ix.dev.nx;
+    info->ny = ix.dev.ny;
+    info->cell_size = ix.dev.cs;
+    info->origin[0] = ix.dev.x0;
+    info->origin[1] = ix.dev.y0;
+    info->device_bytes = ix.bytes;
+    info->build_ms = ix.build_ms;
+    return VCM_OK;
+}
+
+vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm_result *result,
+                       void *stream, vcm_stats *stats) {
+    clear_error();
+    if (!index || !query || !result) return set_error(VCM_E_INVALID, "null argument");
+    if (!result->bin) return set_error(VCM_E_INVALID, "result->bin is required");
+    const Index &ix = index->impl;
+    TargetDesc t;
+    GridDesc g;
+    ParamDesc p;
+    vcm_status st = prepare_query(ix, *query, &t, &g, &p);
+    if (st != VCM_OK) return st;
+    DeviceGuard guard(ix.device);
+    hipStream_t s = (hipStream_t)stream;
+    if (!stats) return launch_brute(ix, t, g, p, *result, 0, g.count, s, nullptr);
+
+    DevStats *d_stats = nullptr;
+    TRY_HIP(hipMalloc(&d_stats, sizeof(DevStats)));
+    hipEvent_t e0, e1;
+    TRY_HIP(hipEventCreate(&e0));
+    TRY_HIP(hipEventCreate(&e1));
+    TRY_HIP(hipMemsetAsync(d_stats, 0, sizeof(DevStats), s));
+    TRY_HIP(hipEventRecord(e0, s));
+    st = launch_brute(ix, t, g, p, *result, 0, g.count, s, d_stats);
+    TRY_HIP(hipEventRecord(e1, s));
+    DevStats h{};
+    TRY_HIP(hipMemcpyAsync(&h, d_stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(d_stats);
+    if (st != VCM_OK) return st;
+    stats->viewpoints = (uint64_t)g.count;
+    stats->rays = h.rays;
+    stats->box_tests = h.box_tests;
+    stats->rechecks = h.rechecks;
+    stats->fp32_disagree = h.fp32_disagree;
+    stats->columns = h.columns;
+    stats->kernel_ms = ms;
+    return VCM_OK;
+}
+
+}  // extern "C"

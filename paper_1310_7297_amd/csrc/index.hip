@@ -1,0 +1,218 @@
+// Device-resident obstacle index: a uniform grid of vertical columns.
+//
+// Replaces the paper's disk-based R*-tree (Sec. III-B), whose purpose there
+// is to fetch only the obstacles near the lines of sight.  Here every column
+// lists the boxes whose footprint, grown by kFatMargin, overlaps it; each
+// list is sorted by decreasing top height so a ray that passes above a box
+// can stop scanning the column there.  Built once per scene and kept in HBM
+// (a few MB even for 100k boxes, so it lives in L2 during traversal).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "vcm_internal.h"
+
+namespace vcm {
+namespace {
+
+struct BuildGrid {
+    float x0, y0, inv_cs;
+    int32_t nx, ny;
+};
+
+__device__ inline void footprint_cols(float lo, float hi, float org, float inv_cs, int32_t n,
+                                      int32_t &a, int32_t &b) {
+    // lo - margin and hi + margin are exact (multiples of 2^-8), and so is the
+    // scaling by the power-of-two inverse cell size.
+    a = static_cast<int32_t>(floorf((lo - kFatMargin - org) * inv_cs));
+    b = static_cast<int32_t>(floorf((hi + kFatMargin - org) * inv_cs));
+    a = max(0, min(n - 1, a));
+    b = max(0, min(n - 1, b));
+}
+
+__global__ void k_count(const float *__restrict__ lo, const float *__restrict__ hi, int64_t n,
+                        BuildGrid g, int32_t *__restrict__ counts) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t ax, bx, ay, by;
+    footprint_cols(lo[i], hi[i], g.x0, g.inv_cs, g.nx, ax, bx);
+    footprint_cols(lo[n + i], hi[n + i], g.y0, g.inv_cs, g.ny, ay, by);
+    for (int32_t y = ay; y <= by; ++y)
+        for (int32_t x = ax; x <= bx; ++x) atomicAdd(&counts[y * g.nx + x], 1);
+}
+
+// Exclusive scan of `n` counts into out[0..n] by one workgroup of 1024.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ counts, int32_t n,
+                                               int32_t *__restrict__ out) {
+    __shared__ int32_t part[1024];
+    const int32_t t = threadIdx.x;
+    const int32_t chunk = (n + 1023) / 1024;
+    const int32_t b = min(n, t * chunk), e = min(n, b + chunk);
+    int32_t s = 0;
+    for (int32_t i = b; i < e; ++i) s += counts[i];
+    part[t] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the 1024 partial sums.
+    for (int32_t off = 1; off < 1024; off <<= 1) {
+        int32_t v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = part[t] - s;
+    for (int32_t i = b; i < e; ++i) {
+        out[i] = run;
+        run += counts[i];
+    }
+    if (t == 1023) out[n] = part[1023];
+}
+
+__global__ void k_fill(const float *__restrict__ lo, const float *__restrict__ hi, int64_t n,
+                       int32_t dim, BuildGrid g, int32_t *__restrict__ cursor,
+                       BoxRec *__restrict__ recs) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    BoxRec r;
+    for (int k = 0; k < 3; ++k) {
+        r.lo[k] = (k < dim) ? lo[k * n + i] : -INFINITY;
+        r.hi[k] = (k < dim) ? hi[k * n + i] : INFINITY;
+    }
+    r.id = static_cast<int32_t>(i);
+    r.pad = 0;
+    int32_t ax, bx, ay, by;
+    footprint_cols(r.lo[0], r.hi[0], g.x0, g.inv_cs, g.nx, ax, bx);
+    footprint_cols(r.lo[1], r.hi[1], g.y0, g.inv_cs, g.ny, ay, by);
+    for (int32_t y = ay; y <= by; ++y)
+        for (int32_t x = ax; x <= bx; ++x) {
+            int32_t slot = atomicAdd(&cursor[y * g.nx + x], 1);
+            recs[slot] = r;
+        }
+}
+
+// Sort each column list by (top height descending, box id ascending), which
+// also makes the index independent of the order the atomics handed out slots.
+__global__ void k_sort(const int32_t *__restrict__ col_start, int32_t ncols,
+                       BoxRec *__restrict__ recs) {
+    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    const int32_t b = col_start[c], e = col_start[c + 1];
+    for (int32_t i = b + 1; i < e; ++i) {
+        BoxRec key = recs[i];
+        int32_t j = i - 1;
+        while (j >= b) {
+            const BoxRec &o = recs[j];
+            bool after = (o.hi[2] < key.hi[2]) || (o.hi[2] == key.hi[2] && o.id > key.id);
+            if (!after) break;
+            recs[j + 1] = o;
+            --j;
+        }
+        recs[j + 1] = key;
+    }
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return set_error(e_ == hipErrorOutOfMemory ? VCM_E_NOMEM : VCM_E_DEVICE,        \
+                             std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+}  // namespace
+
+vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, int64_t n,
+                              double cell_size, hipStream_t stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    // Column grid over the grown footprints.
+    double mnx = 0, mny = 0, mxx = 0, mxy = 0;
+    if (n > 0) {
+        mnx = mny = 1e30;
+        mxx = mxy = -1e30;
+        for (int64_t i = 0; i < n; ++i) {
+            mnx = std::min(mnx, (double)h_lo[i]);
+            mny = std::min(mny, (double)h_lo[n + i]);
+            mxx = std::max(mxx, (double)h_hi[i]);
+            mxy = std::max(mxy, (double)h_hi[n + i]);
+        }
+    }
+    double cs = cell_size;
+    if (cs <= 0) {
+        double area = std::max(1.0, (mxx - mnx) * (mxy - mny));
+        double side = std::sqrt(area / std::max<int64_t>(n, 1));
+        cs = std::ldexp(1.0, (int)std::lround(std::log2(std::max(side, 1.0))));
+        cs = std::min(std::max(cs, 1.0), 1024.0);
+    }
+    int e2;
+    if (std::frexp(cs, &e2) != 0.5 || cs < 1.0 / 16 || cs > 4096)
+        return set_error(VCM_E_INVALID, "cell_size must be a power of two in [1/16, 4096]");
+    double x0 = std::floor((mnx - kFatMargin) / cs) * cs;
+    double y0 = std::floor((mny - kFatMargin) / cs) * cs;
+    int64_t nx = (int64_t)std::floor((mxx + kFatMargin - x0) / cs) + 1;
+    int64_t ny = (int64_t)std::floor((mxy + kFatMargin - y0) / cs) + 1;
+    while (nx * ny > (int64_t(1) << 24)) {
+        cs *= 2;
+        x0 = std::floor((mnx - kFatMargin) / cs) * cs;
+        y0 = std::floor((mny - kFatMargin) / cs) * cs;
+        nx = (int64_t)std::floor((mxx + kFatMargin - x0) / cs) + 1;
+        ny = (int64_t)std::floor((mxy + kFatMargin - y0) / cs) + 1;
+    }
+    const int32_t ncols = (int32_t)(nx * ny);
+    BuildGrid g{(float)x0, (float)y0, (float)(1.0 / cs), (int32_t)nx, (int32_t)ny};
+
+    float *d_lo = nullptr, *d_hi = nullptr;
+    int32_t *d_counts = nullptr, *d_cursor = nullptr;
+    const size_t nb = (size_t)std::max<int64_t>(n, 1) * 3 * sizeof(float);
+    HIP_TRY(hipMalloc(&d_lo, nb));
+    HIP_TRY(hipMalloc(&d_hi, nb));
+    HIP_TRY(hipMalloc(&d_counts, sizeof(int32_t) * ncols));
+    HIP_TRY(hipMalloc(&ix->d_col_start, sizeof(int32_t) * (ncols + 1)));
+    HIP_TRY(hipMalloc(&d_cursor, sizeof(int32_t) * ncols));
+    if (n > 0) {
+        HIP_TRY(hipMemcpyAsync(d_lo, h_lo, sizeof(float) * 3 * n, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_hi, h_hi, sizeof(float) * 3 * n, hipMemcpyHostToDevice, stream));
+    }
+    HIP_TRY(hipMemsetAsync(d_counts, 0, sizeof(int32_t) * ncols, stream));
+    const int T = 256;
+    if (n > 0)
+        hipLaunchKernelGGL(k_count, dim3((unsigned)((n + T - 1) / T)), dim3(T), 0, stream, d_lo,
+                           d_hi, n, g, d_counts);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, d_counts, ncols, ix->d_col_start);
+    HIP_TRY(hipGetLastError());
+    int32_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, ix->d_col_start + ncols, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipMalloc(&ix->d_recs, sizeof(BoxRec) * std::max(total, 1)));
+    HIP_TRY(hipMemcpyAsync(d_cursor, ix->d_col_start, sizeof(int32_t) * ncols,
+                           hipMemcpyDeviceToDevice, stream));
+    if (n > 0)
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + T - 1) / T)), dim3(T), 0, stream, d_lo,
+                           d_hi, n, ix->dim, g, d_cursor, ix->d_recs);
+    hipLaunchKernelGGL(k_sort, dim3((unsigned)((ncols + T - 1) / T)), dim3(T), 0, stream,
+                       ix->d_col_start, ncols, ix->d_recs);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(stream));
+    hipFree(d_lo);
+    hipFree(d_hi);
+    hipFree(d_counts);
+    hipFree(d_cursor);
+
+    ix->n_boxes = n;
+    ix->n_refs = total;
+    ix->dev.col_start = ix->d_col_start;
+    ix->dev.recs = ix->d_recs;
+    ix->dev.x0 = (float)x0;
+    ix->dev.y0 = (float)y0;
+    ix->dev.cs = (float)cs;
+    ix->dev.inv_cs = (float)(1.0 / cs);
+    ix->dev.nx = (int32_t)nx;
+    ix->dev.ny = (int32_t)ny;
+    ix->dev.dim = ix->dim;
+    ix->bytes = sizeof(int32_t) * (ncols + 1) + sizeof(BoxRec) * std::max(total, 1);
+    ix->build_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return VCM_OK;
+}
+
+}  // namespace vcm

@@ -1,0 +1,50 @@
+"""The C-ABI library loads and exports every symbol include/vcm.h declares;
+argument validation that precedes any device work (no GPU needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1310_7297_amd as vcm
+from paper_1310_7297_amd import scenes
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "vcm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vcm_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    L = vcm.load_library()
+    names = declared_functions()
+    assert names, "no declarations found"
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(vcm.EXPORTS)
+
+
+def test_version():
+    assert "gfx950" in vcm.vcm_version()
+
+
+@pytest.mark.parametrize("bad", ["non_dyadic", "inverted", "range", "dim"])
+def test_build_index_rejects(bad):
+    lo = np.array([[0.0], [0.0], [0.0]])
+    hi = np.array([[1.0], [1.0], [1.0]])
+    dim = 3
+    if bad == "non_dyadic":
+        lo[0, 0] = 0.1
+    elif bad == "inverted":
+        lo[1, 0] = 2.0
+    elif bad == "range":
+        hi[0, 0] = 20000.0
+    else:
+        dim = 4
+    with pytest.raises(vcm.VcmError) as e:
+        vcm.vcm_build_index(scenes.Scene(dim, lo, hi))
+    assert e.value.status == vcm.VCM_E_INVALID
+    assert vcm.vcm_last_error()

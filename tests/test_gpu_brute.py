@@ -1,0 +1,186 @@
+"""Parity of the HIP brute-force path (through the C-ABI) with the oracle."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1310_7297_amd as vcm
+from paper_1310_7297_amd import scenes
+from paper_1310_7297_amd.scenes import (BILLBOARD, BIN_LOG, CUBE, FRACTION, FULL, SEGMENT,
+                                         Grid, Params, Query, Scene, Target)
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    vcm.load_library()
+
+
+def _gpu_map(scene, query, precision=vcm.VCM_FP32_RECHECK, stats=False, cell_size=0.0):
+    idx = vcm.vcm_build_index(scene, cell_size=cell_size)
+    out = vcm.compute_map(idx, query, stats=stats, precision=precision)
+    idx.free()
+    return out
+
+
+def _with(query, **kw):
+    p = Params(**{**query.params.__dict__, **kw})
+    return Query(query.target, query.grid, p)
+
+
+def _near_target(grid, target, radius, limit, seed):
+    """Viewpoint indices within `radius` of the target centre (seeded subset)."""
+    n = np.array(grid.n)
+    h2 = np.array(grid.extent) / (2 * n)
+    c = np.array(target.center)
+    lo = np.maximum(0, np.floor((c - radius - np.array(grid.origin)) / (2 * h2)).astype(int))
+    hi = np.minimum(n - 1, np.ceil((c + radius - np.array(grid.origin)) / (2 * h2)).astype(int))
+    ii, jj, kk = np.meshgrid(np.arange(lo[0], hi[0] + 1), np.arange(lo[1], hi[1] + 1),
+                             np.arange(lo[2], hi[2] + 1), indexing="ij")
+    idx = (ii + n[0] * (jj + n[1] * kk)).ravel()
+    rng = np.random.default_rng(seed)
+    if len(idx) > limit:
+        idx = rng.choice(idx, limit, replace=False)
+    return np.sort(idx).astype(np.int64)
+
+
+# ---------------------------------------------------------------- 2-D --------
+
+@pytest.mark.parametrize("precision", [vcm.VCM_FP64, vcm.VCM_FP32_RECHECK])
+@pytest.mark.parametrize("mode", [FULL, FRACTION])
+@pytest.mark.parametrize("scale", [0, BIN_LOG])
+def test_config1_full_map(precision, mode, scale):
+    scene, q = scenes.config1()
+    q = _with(q, mode=mode, bin_scale=scale)
+    g = _gpu_map(scene, q, precision=precision)
+    o = oracle.vcm_eval(scene, q)
+    compare(g, o, q.params.n_bins, label=f"config1 p{precision} m{mode} s{scale}")
+    assert (o["count"] > 0).sum() > 100
+
+
+# ---------------------------------------------------------------- tiny -------
+
+def _tiny(seed):
+    dim = 2 if seed % 3 == 0 else 3
+    sc = scenes.random_boxes(10, seed, extent=32.0, max_side=8.0, dim=dim, grid_step=2.0)
+    if dim == 2:
+        t = Target(SEGMENT, (16.0, 16.0, 0.0), (4.0, 0.0), normal_axis=seed % 2, samples_u=8, samples_v=1)
+        g = Grid((0.0, 0.0, 0.0), (32.0, 32.0, 0.0), (16, 16, 1))
+    elif seed % 3 == 1:
+        t = Target(BILLBOARD, (16.0, 16.0, 4.0), (4.0, 2.0), normal_axis=seed % 2, samples_u=4,
+                   samples_v=2, normal_sign=1 if seed % 4 < 2 else -1)
+        g = Grid((0.0, 0.0, 0.0), (32.0, 32.0, 16.0), (16, 16, 8))
+    else:
+        t = Target(CUBE, (16.0, 16.0, 4.0), (4.0, 0.0), samples_u=2, samples_v=2)
+        g = Grid((0.0, 0.0, 0.0), (32.0, 32.0, 16.0), (16, 16, 8))
+    tlo, thi = t.aabb()
+    ov = np.ones(sc.n, bool)
+    for k in range(dim):
+        ov &= (sc.lo[k] <= thi[k]) & (sc.hi[k] >= tlo[k])
+    return Scene(dim, sc.lo[:, ~ov], sc.hi[:, ~ov]), t, g
+
+
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("mode", [FULL, FRACTION])
+def test_tiny_lattice_scenes(seed, mode):
+    """Lattice-aligned boxes and viewpoints: rays in face planes, through edges
+    and corners, viewpoints on box faces; several column sizes."""
+    sc, t, g = _tiny(seed)
+    fovs = [360.0] if t.kind == CUBE else [360.0, 300.0, 240.0, 180.0, 120.0, 60.0, 90.0]
+    for fov in fovs:
+        q = Query(t, g, Params(n_bins=16, mode=mode, fov_deg=fov, bin_scale=BIN_LOG))
+        o = oracle.vcm_eval(sc, q)
+        for cs in (0.0, 1.0, 4.0, 16.0):
+            gm = _gpu_map(sc, q, cell_size=cs)
+            compare(gm, o, 16, label=f"tiny seed {seed} fov {fov} cs {cs}")
+
+
+def test_empty_scene_and_single_viewpoint():
+    t = Target(BILLBOARD, (0.0, 0.0, 10.0), (8.0, 4.0), normal_axis=0, samples_u=16, samples_v=8)
+    sc = Scene(3, np.zeros((3, 0)), np.zeros((3, 0)))
+    for g in (Grid((-64.0, -40.0, 0.0), (112.0, 80.0, 24.0), (7, 5, 3)),
+              Grid((8.0, 8.0, 8.0), (2.0, 2.0, 2.0), (1, 1, 1))):
+        q = Query(t, g, Params(n_bins=16, bin_scale=BIN_LOG))
+        compare(_gpu_map(sc, q), oracle.vcm_eval(sc, q), 16, label="empty")
+
+
+# ---------------------------------------------------------------- 3-D configs --
+
+def _sampled(cfg, mode, n_random, n_near, radius, seed):
+    scene, q = cfg()
+    q = _with(q, mode=mode)
+    g = _gpu_map(scene, q)   # the full map, in the benchmark's launch configuration
+    vp = np.unique(np.concatenate([scenes.viewpoint_sample(q.grid, n_random, seed),
+                                   _near_target(q.grid, q.target, radius, n_near, seed)]))
+    o = oracle.vcm_eval(scene, q, vp, nthreads=NT)
+    r = compare(g, o, q.params.n_bins, idx=vp, label=cfg.__name__)
+    assert (o["count"] > 0).sum() > 20, "sample hit too few visible viewpoints"
+    return g, o, vp
+
+
+@pytest.mark.parametrize("mode", [FRACTION, FULL])
+def test_config2_sampled(mode):
+    _sampled(scenes.config2, mode, 400, 600, 120.0, 2)
+
+
+@pytest.mark.parametrize("mode", [FRACTION, FULL])
+def test_config3_sampled(mode):
+    _sampled(scenes.config3, mode, 300, 500, 150.0, 3)
+
+
+def test_config2_full_vs_fraction_consistent():
+    """Properties at full size: FULL count is N(q) or 0 and equals N(q) exactly
+    where the FRACTION count is N(q); colours are 0 where counts are 0."""
+    scene, q = scenes.config2()
+    gf = _gpu_map(scene, _with(q, mode=FULL))
+    gr = _gpu_map(scene, _with(q, mode=FRACTION))
+    full = gf["count"].astype(int)
+    frac = gr["count"].astype(int)
+    assert set(np.unique(full)) <= {0, 128}
+    assert np.array_equal(full == 128, frac == 128)
+    assert np.all(gr["c"][frac == 0] == 0) and np.all(gf["c"][full == 0] == 0)
+    assert np.all(frac <= 128)
+
+
+def test_recheck_everything_matches_default_and_no_disagreement():
+    """Every ray test settled by the exact float64 predicate gives the same map,
+    and no float32 decision outside the margin disagreed with it."""
+    scene, q = scenes.config2()
+    q = Query(q.target, Grid((800.0, 800.0, 0.0), (400.0, 400.0, 150.0), (64, 64, 32)),
+              Params(n_bins=16, mode=FRACTION))
+    a = _gpu_map(scene, q, stats=True)
+    b = _gpu_map(scene, _with(q, recheck_eps=math.inf), stats=True)
+    assert np.array_equal(a["count"], b["count"]) and np.array_equal(a["bin"], b["bin"])
+    assert np.array_equal(a["c"], b["c"])
+    assert b["stats"]["fp32_disagree"] == 0
+    assert b["stats"]["rechecks"] == b["stats"]["box_tests"] > 0
+    assert a["stats"]["rechecks"] < 1e-3 * a["stats"]["box_tests"]
+    # the same with no margin at all must still be exact where it matters: the
+    # disagreement counter only counts decisions outside the default margin
+    assert a["stats"]["rays"] == b["stats"]["rays"]
+
+
+def test_invalid_queries_rejected():
+    scene, q = scenes.config1()
+    idx = vcm.vcm_build_index(scene)
+    bad = [
+        _with(q, n_bins=1),
+        _with(q, fov_deg=0.0),
+        Query(q.target, Grid((0.1, 0.0, 0.0), (1000.0, 1000.0, 0.0), (64, 64, 1)), q.params),
+        Query(q.target, Grid((0.0, 0.0, 0.0), (1000.0, 1000.0, 0.0), (3, 64, 1)), q.params),
+        Query(Target(CUBE, (500.0, 500.0, 0.0), (4.0, 0.0)), q.grid, q.params),
+    ]
+    import torch
+    b, c, cnt = vcm.alloc_result(q.grid.count)
+    for bq in bad:
+        with pytest.raises(vcm.VcmError) as e:
+            vcm.vcm_compute(idx, bq, b, c, cnt)
+        assert e.value.status == vcm.VCM_E_INVALID
+    idx.free()
