@@ -36,7 +36,21 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe(mib: int):
+    """A plain copy kernel of known size: reads and writes `mib` MiB once."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copy probe: {mib} MiB read and written per copy, 3 copies", flush=True)
 
 
 def timed_steps(vcm, idx, q, bufs, steps, warmup):
@@ -61,6 +75,9 @@ def timed_steps(vcm, idx, q, bufs, steps, warmup):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards by viewpoint tiles with no exchange; see the design notes)",
