@@ -118,6 +118,8 @@ def main():
                 "kernel": "k_brute", "kernel_ms": kernel_ms,
                 "box_tests_per_launch": st["box_tests"], "columns_per_launch": st["columns"],
                 "rechecks_per_launch": st["rechecks"],
+                "slot_tests_per_launch": st.get("slot_tests"),
+                "inside_box_viewpoints": st.get("inside_box"),
                 "hbm_bytes_algorithmic": 7 * n_vp,
                 "hbm_frac": 7 * n_vp / (kernel_ms * 1e-3) / PEAK_HBM}
 

@@ -177,6 +177,8 @@ typedef struct {
                                 taken with the default margin, that differ
                                 from the exact predicate (must be 0)        */
     uint64_t columns;        /* grid columns visited                         */
+    uint64_t slot_tests;     /* wavefront-level slab tests (64 lanes each)   */
+    uint64_t inside_box;     /* viewpoints found inside an obstacle          */
     double kernel_ms;        /* device time of the call's kernels            */
 } vcm_stats;
 

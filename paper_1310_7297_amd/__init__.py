@@ -82,6 +82,7 @@ class vcm_stats(ctypes.Structure):
     _fields_ = [("viewpoints", ctypes.c_uint64), ("rays", ctypes.c_uint64),
                 ("box_tests", ctypes.c_uint64), ("rechecks", ctypes.c_uint64),
                 ("fp32_disagree", ctypes.c_uint64), ("columns", ctypes.c_uint64),
+                ("slot_tests", ctypes.c_uint64), ("inside_box", ctypes.c_uint64),
                 ("kernel_ms", ctypes.c_double)]
 
 
@@ -92,11 +93,14 @@ class vcm_result(ctypes.Structure):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load libvcm.so (after torch, so both share one HIP runtime)."""
+def load_library(path: Optional[str] = None):
+    """Load libvcm.so (after torch, so both share one HIP runtime).
+
+    VCM_LIB overrides the path (to compare two builds of the library)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("VCM_LIB") or LIB_PATH
     try:
         import torch  # noqa: F401  (loads the HIP runtime libvcm links against)
     except ImportError:

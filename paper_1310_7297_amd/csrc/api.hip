@@ -1,6 +1,7 @@
 // C-ABI entry points: argument validation, ownership, launches.
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -106,6 +107,7 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
         count *= G.n[k];
     }
     if (dim == 2 && G.n[2] != 1) return set_error(VCM_E_INVALID, "2-D grids have n[2] == 1");
+    if (G.n[1] > 65535) return set_error(VCM_E_INVALID, "grid n[1] must be <= 65535");
     double h2[3] = {0, 0, 0};
     for (int k = 0; k < dim; ++k) {
         if (!(G.extent[k] >= 0)) return set_error(VCM_E_INVALID, "grid extent must be >= 0");
@@ -142,8 +144,11 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
     t->su = T.samples_u;
     t->sv = T.samples_v;
     t->per_facet = per_facet;
+    t->m_pf = (uint64_t)((0x100000000ull + per_facet - 1) / per_facet);
+    t->m_su = (uint64_t)((0x100000000ull + T.samples_u - 1) / T.samples_u);
+    // kernels work in the index frame (exact translation)
     for (int k = 0; k < 3; ++k) {
-        t->c[k] = (k < dim) ? (float)T.center[k] : 0.0f;
+        t->c[k] = (k < dim) ? (float)(T.center[k] - ix.frame[k]) : 0.0f;
         t->half[k] = (float)half[k];
     }
     t->hu = (float)hu;
@@ -152,7 +157,7 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
 
     *g = GridDesc{};
     for (int k = 0; k < 3; ++k) {
-        g->o[k] = (k < dim) ? (float)G.origin[k] : 0.0f;
+        g->o[k] = (k < dim) ? (float)(G.origin[k] - ix.frame[k]) : 0.0f;
         g->h2[k] = (float)h2[k];
         g->n[k] = G.n[k];
     }
@@ -183,9 +188,10 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
     p->inv_V0 = (float)(1.0 / V0);
     p->mu = (float)mu;
     p->inv_log_V0_mu = (float)(1.0 / std::log(V0 / mu));
-    p->recheck_all = std::isinf(P.recheck_eps) ? 1 : 0;
-    p->eps = std::isinf(P.recheck_eps) ? 0x1p-20f : (float)P.recheck_eps;
+    p->eps = (float)P.recheck_eps;  // +inf stays +inf: every test goes to the exact predicate
+    p->eps_ref = 0x1p-20f;
     p->fp64 = P.precision == VCM_FP64 ? 1 : 0;
+
     return VCM_OK;
 }
 
@@ -265,8 +271,8 @@ vcm_status vcm_index_get_info(const vcm_index *index, vcm_index_info *info) {
     info->nx = ix.dev.nx;
     info->ny = ix.dev.ny;
     info->cell_size = ix.dev.cs;
-    info->origin[0] = ix.dev.x0;
-    info->origin[1] = ix.dev.y0;
+    info->origin[0] = ix.frame[0];
+    info->origin[1] = ix.frame[1];
     info->device_bytes = ix.bytes;
     info->build_ms = ix.build_ms;
     return VCM_OK;
@@ -285,7 +291,7 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     if (st != VCM_OK) return st;
     DeviceGuard guard(ix.device);
     hipStream_t s = (hipStream_t)stream;
-    if (!stats) return launch_brute(ix, t, g, p, *result, 0, g.count, s, nullptr);
+    if (!stats) return launch_brute(ix, t, g, p, *result, s, nullptr);
 
     DevStats *d_stats = nullptr;
     TRY_HIP(hipMalloc(&d_stats, sizeof(DevStats)));
@@ -294,7 +300,7 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     TRY_HIP(hipEventCreate(&e1));
     TRY_HIP(hipMemsetAsync(d_stats, 0, sizeof(DevStats), s));
     TRY_HIP(hipEventRecord(e0, s));
-    st = launch_brute(ix, t, g, p, *result, 0, g.count, s, d_stats);
+    st = launch_brute(ix, t, g, p, *result, s, d_stats);
     TRY_HIP(hipEventRecord(e1, s));
     DevStats h{};
     TRY_HIP(hipMemcpyAsync(&h, d_stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
@@ -311,6 +317,8 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     stats->rechecks = h.rechecks;
     stats->fp32_disagree = h.fp32_disagree;
     stats->columns = h.columns;
+    stats->slot_tests = h.slot_tests;
+    stats->inside_box = h.inside_box;
     stats->kernel_ms = ms;
     return VCM_OK;
 }

@@ -14,6 +14,7 @@
 //   * each lane runs a float32 slab test per ray; a result within `eps` of
 //     the decision boundary is settled by the exact float64 predicate;
 //   * visibility is reduced with wave ballots and popcounts (integers only).
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -25,80 +26,36 @@ namespace {
 constexpr float kWalkMargin = 1.0f / 128.0f;
 constexpr float kLambdaMargin = 1e-6f;
 
-// Exact contact of the closed segment [q, s] with the closed box B.
-// All coordinates are multiples of 2^-8 below 2^14, so every difference and
-// every product of two differences below is exact in float64.  Along each
-// axis the box admits the ray parameters between an entry and an exit
-// fraction (numerator / positive denominator); the segment meets the box iff
-// no entry exceeds an exit, [0, 1] included, compared by cross-multiplying.
+// Exact contact of the closed segment [q, s] with the closed box [lo, hi],
+// given d = s - q, lq = lo - q and hq = hi - q.  All coordinates are
+// multiples of 2^-8 below 2^14, so these differences are exact in float32
+// and every product of two of them is exact in float64.  Along each axis the
+// box admits the ray parameters between an entry and an exit fraction
+// (numerator / positive denominator); the segment meets the box iff no entry
+// exceeds an exit, the bounds 0 and 1 included, compared by cross-multiplying.
 template <int DIM>
-__device__ __noinline__ bool exact_contact(float qx, float qy, float qz, float sx, float sy,
-                                           float sz, float lx, float ly, float lz, float hx,
-                                           float hy, float hz) {
-    const double q[3] = {qx, qy, qz}, s[3] = {sx, sy, sz};
-    const double lo[3] = {lx, ly, lz}, hi[3] = {hx, hy, hz};
-    double en[DIM], ex[DIM], de[DIM];
-    bool moving[DIM];
+__device__ __attribute__((always_inline)) inline bool exact_contact(const float *d,
+                                                                    const float *lq,
+                                                                    const float *hq) {
+    float en[DIM], ex[DIM], de[DIM];
+    bool ok = true;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        const double dk = s[k] - q[k];
-        moving[k] = dk != 0.0;
-        if (!moving[k]) {
-            if (q[k] < lo[k] || q[k] > hi[k]) return false;
-            en[k] = 0.0;
-            ex[k] = 1.0;
-            de[k] = 1.0;
-            continue;
-        }
-        const bool up = dk > 0.0;
-        en[k] = up ? lo[k] - q[k] : q[k] - hi[k];
-        ex[k] = up ? hi[k] - q[k] : q[k] - lo[k];
-        de[k] = fabs(dk);
-        if (en[k] > de[k] || ex[k] < 0.0) return false;
+        const bool up = d[k] > 0.0f, down = d[k] < 0.0f;
+        en[k] = up ? lq[k] : (down ? -hq[k] : 0.0f);
+        ex[k] = up ? hq[k] : (down ? -lq[k] : 1.0f);
+        de[k] = up ? d[k] : (down ? -d[k] : 1.0f);
+        // a direction component of 0: q itself must lie in the slab
+        ok = ok && (up || down || (lq[k] <= 0.0f && hq[k] >= 0.0f));
+        ok = ok && en[k] <= de[k] && ex[k] >= 0.0f;
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
         for (int b = 0; b < DIM; ++b)
-            if (a != b && moving[a] && moving[b] && en[a] * de[b] > ex[b] * de[a]) return false;
-    return true;
-}
-
-template <int DIM>
-__device__ inline bool exact_contact(const float *q, const float *s, const BoxRec &B) {
-    return exact_contact<DIM>(q[0], q[1], q[2], s[0], s[1], s[2], B.lo[0], B.lo[1], B.lo[2],
-                              B.hi[0], B.hi[1], B.hi[2]);
-}
-
-// Lane-private ray data for one slot.
-struct Ray {
-    float s[3];    // sample position
-    float inv[3];  // 1 / (s - q), 0 where the component is 0
-    bool zero[3];  // component of s - q is exactly 0
-    bool live;
-};
-
-// Float32 slab test.  lq = lo - q and hq = hi - q are exact.  Returns the
-// entry/exit gap t1 - t0 of the parameter interval the box cuts from [0, 1]:
-// the segment meets the box iff the gap is >= 0.  With ZERO the axes whose
-// direction component is 0 are handled by containment.
-template <int DIM, bool ZERO>
-__device__ inline float slab_gap(const Ray &r, const float *lq, const float *hq) {
-    float t0 = 0.0f, t1 = 1.0f;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        const float a = lq[k] * r.inv[k];
-        const float b = hq[k] * r.inv[k];
-        float mn = fminf(a, b), mx = fmaxf(a, b);
-        if (ZERO) {
-            const bool inside = lq[k] <= 0.0f && hq[k] >= 0.0f;
-            mn = r.zero[k] ? (inside ? -INFINITY : INFINITY) : mn;
-            mx = r.zero[k] ? (inside ? INFINITY : -INFINITY) : mx;
-        }
-        t0 = fmaxf(t0, mn);
-        t1 = fminf(t1, mx);
-    }
-    return t1 - t0;
+            if (a != b)
+                ok = ok && double(en[a]) * double(de[b]) <= double(ex[b]) * double(de[a]);
+    return ok;
 }
 
 __device__ inline unsigned long long ballot(bool p) { return __ballot(p); }
@@ -161,248 +118,499 @@ __device__ inline bool in_fov(const TargetDesc &T, const ParamDesc &P, const flo
     return dn >= 0.0 || dn * dn <= P.fov_c2 * d2;
 }
 
-template <int DIM, int NS, bool EXACT64, bool STATS>
-__global__ __launch_bounds__(256) void k_brute(BruteArgs A) {
-    using R = typename std::conditional<EXACT64, double, float>::type;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t vp = A.vp_begin + static_cast<int64_t>(blockIdx.x) * 4 + wave;
-    if (vp >= A.vp_end) return;
+
+__device__ inline float readlane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline unsigned long long lanes_below() {
+    return (1ull << (threadIdx.x & 63)) - 1ull;
+}
+__device__ inline int mbcnt(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(m), 0u));
+}
+
+// Position of sample `si` among the live samples of a viewpoint whose live
+// facets are `faces` (cube) or the single facet (segment, billboard).
+template <int DIM>
+__device__ __attribute__((always_inline)) inline void sample_pos(const TargetDesc &T, unsigned faces, unsigned si, float *s) {
+    const unsigned f = static_cast<unsigned>((si * T.m_pf) >> 32);
+    const unsigned w = si - f * T.per_facet;
+    const unsigned iv = static_cast<unsigned>((w * T.m_su) >> 32);
+    const unsigned iu = w - iv * T.su;
+    const float u = static_cast<float>(2 * static_cast<int>(iu) + 1 - T.su) * T.hu;
+    const float v = static_cast<float>(2 * static_cast<int>(iv) + 1 - T.sv) * T.hv;
+    s[0] = T.c[0];
+    s[1] = T.c[1];
+    s[2] = DIM == 3 ? T.c[2] : 0.0f;
+    if (T.kind == VCM_CUBE) {
+        const int fc = static_cast<int>((faces >> (4 * f)) & 7u);
+        const int k = fc >> 1;
+        const int ua = (k == 0) ? 1 : 0, vb = (k == 2) ? 1 : 2;
+        const float ck = k == 0 ? T.c[0] : (k == 1 ? T.c[1] : T.c[2]);
+        const float hk = k == 0 ? T.half[0] : (k == 1 ? T.half[1] : T.half[2]);
+        const float plane = (fc & 1) ? ck + hk : ck - hk;
+        s[0] = k == 0 ? plane : (ua == 0 ? T.c[0] + u : s[0]);
+        s[1] = k == 1 ? plane : (ua == 1 ? T.c[1] + u : T.c[1] + v);
+        s[2] = k == 2 ? plane : T.c[2] + v;
+    } else {
+        const int wax = 1 - T.nax;
+        if (wax == 0) s[0] = T.c[0] + u;
+        else s[1] = T.c[1] + u;
+        if (T.kind == VCM_BILLBOARD) s[2] = T.c[2] + v;
+    }
+}
+
+// Rays of one slot: sample position and reciprocal direction per lane.  A
+// zero direction component gets reciprocal 0 and sends the lane's tests to
+// the exact predicate (zero_lane).
+template <int DIM>
+__device__ __attribute__((always_inline)) inline bool ray_setup(const TargetDesc &T, unsigned faces, const float *q,
+                                 unsigned si, float *s, float *inv) {
+    sample_pos<DIM>(T, faces, si, s);
+    bool zero = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float d = s[k] - q[k];
+        // v_rcp_f32 is accurate to 1 ulp; with the exact numerator lo - q the
+        // slab parameter carries at most 1.5 * 2^-23 relative error.
+        inv[k] = (k < DIM && d != 0.0f) ? __builtin_amdgcn_rcpf(d) : 0.0f;
+        zero = zero || (k < DIM && d == 0.0f);
+    }
+    return zero;
+}
+
+// Float32 slab test: gap t1 - t0 of the parameter interval [t0, t1] that the
+// box cuts from [0, 1]; the segment meets the box iff gap >= 0.
+template <int DIM>
+__device__ inline float slab_gap(const float *inv, const float *lq, const float *hq) {
+    float t0 = 0.0f, t1 = 1.0f;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const float a = lq[k] * inv[k];
+        const float b = hq[k] * inv[k];
+        t0 = fmaxf(t0, fminf(a, b));
+        t1 = fminf(t1, fmaxf(a, b));
+    }
+    return t1 - t0;
+}
+
+struct WaveStats {
+    unsigned long long tests = 0, slots = 0, rechecks = 0, cols = 0, rays = 0, inside = 0;
+};
+
+// A non-negative float as an unsigned integer with the same order; negative
+// values (and -0) map to 0, below every box coordinate of the index frame.
+__device__ inline unsigned ord(float x) { return x > 0.0f ? __float_as_uint(x) : 0u; }
+
+// The index is immutable while kernels run: read it through the constant
+// address space, so that wave-uniform reads become scalar loads.
+// (The host pass of the compiler only needs the declarations.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define VCM_CONST __attribute__((address_space(4)))
+#else
+#define VCM_CONST
+#endif
+typedef const VCM_CONST int32_t *cptr_i32;
+typedef const VCM_CONST BoxRec *cptr_rec;
+
+// Visibility of the live samples from q for one wavefront.  Returns the
+// number of unblocked live samples (FULL mode: exact only when it equals N).
+//
+// Box records arrive by scalar loads; the records that cannot meet the
+// corridor (top below its lowest point, or beside its extent along b) are
+// rejected by integer compares on the scalar unit, so only candidates cost
+// vector instructions.
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
+__device__ __attribute__((always_inline)) inline int trace_viewpoint(
+    const BruteArgs &A, cptr_i32 col_start, cptr_rec recs, const float *q, unsigned faces,
+    int N, int *lds, WaveStats &ws,
+    unsigned long long &n_disagree) {
     const TargetDesc &T = A.tgt;
     const ParamDesc &P = A.prm;
     const DevIndex &X = A.idx;
+    const int lane = threadIdx.x & 63;
 
-    // Viewpoint position (exact).
-    const int64_t n0 = A.grid.n[0], n1 = A.grid.n[1];
-    const int64_t ii[3] = {vp % n0, (vp / n0) % n1, vp / (n0 * n1)};
-    float q[3];
+    // ---- a viewpoint inside (or on) an obstacle sees nothing
+    {
+        const int cx = static_cast<int>(floorf(q[0] * X.inv_cs));
+        const int cy = static_cast<int>(floorf(q[1] * X.inv_cs));
+        if (cx >= 0 && cx < X.nx && cy >= 0 && cy < X.ny) {
+            const int col = cx + X.nx * cy;
+            const int rb = col_start[col], re = col_start[col + 1];
+            for (int rr = rb; rr < re; ++rr) {
+                const BoxRec B = recs[rr];
+                if (DIM == 3 && B.hi[2] < q[2]) break;
+                bool in = true;
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-        q[k] = (k < DIM) ? A.grid.o[k] + static_cast<float>(2 * ii[k] + 1) * A.grid.h2[k] : 0.0f;
-
-    // Live facets: the segment / billboard facet always; cube faces whose
-    // outer side contains q strictly.
-    int faces[3] = {0, 0, 0};
-    int nf = 0;
-    if (T.kind == VCM_CUBE) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (q[k] > T.c[k] + T.half[k]) faces[nf++] = 2 * k + 1;
-            else if (q[k] < T.c[k] - T.half[k]) faces[nf++] = 2 * k;
+                for (int k = 0; k < DIM; ++k) in = in && B.lo[k] <= q[k] && q[k] <= B.hi[k];
+                if (in) {
+                    if (STATS) ++ws.inside;
+                    return 0;
+                }
+            }
         }
-    } else {
-        nf = 1;
     }
-    const int N = nf * T.per_facet;
-    const bool fov = in_fov<DIM>(T, P, q);
-    const R craw = raw_colour<DIM, R>(T, P, q);
 
-    int visible = 0;
-    unsigned long long n_tests = 0, n_rechecks = 0, n_disagree = 0, n_cols = 0;
-
-    if (fov && N > 0) {
-        // ---- ray setup: slot j, lane l holds sample j*64 + l
-        Ray ray[NS];
-        bool blk[NS];
-        bool act[NS];   // wave-uniform: some live ray of the slot is unresolved
-        bool zro[NS];   // wave-uniform: some ray of the slot has a zero component
+    // ---- rays: slot j, lane l holds live sample j*64 + l
+    float iv[NS][3];
+    int sidx[NS];
+    bool zl[NS];  // the lane's ray has a zero direction component
+    unsigned long long open[NS];
 #pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            const int si = j * 64 + lane;
-            Ray &r = ray[j];
-            r.live = si < N;
-            const int f = r.live ? si / T.per_facet : 0;
-            const int w = r.live ? si - f * T.per_facet : 0;
-            const int iu = w % T.su, iv = w / T.su;
-            const float u = static_cast<float>(2 * iu + 1 - T.su) * T.hu;
-            const float v = static_cast<float>(2 * iv + 1 - T.sv) * T.hv;
-            float s[3] = {T.c[0], T.c[1], DIM == 3 ? T.c[2] : 0.0f};
-            if (T.kind == VCM_CUBE) {
-                const int fc = f == 0 ? faces[0] : (f == 1 ? faces[1] : faces[2]);
-                const int k = fc >> 1;
-                const int ua = (k == 0) ? 1 : 0, vb = (k == 2) ? 1 : 2;
-                s[k] = (fc & 1) ? T.c[k] + T.half[k] : T.c[k] - T.half[k];
-                s[ua] = T.c[ua] + u;
-                s[vb] = T.c[vb] + v;
-            } else {
-                const int wax = 1 - T.nax;
-                s[wax] = T.c[wax] + u;
-                if (T.kind == VCM_BILLBOARD) s[2] = T.c[2] + v;
-            }
-            bool anyzero = false;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                r.s[k] = s[k];
-                const float d = s[k] - q[k];
-                r.zero[k] = (k < DIM) && d == 0.0f;
-                r.inv[k] = (k < DIM && d != 0.0f) ? 1.0f / d : 0.0f;
-                anyzero |= r.zero[k];
-            }
-            blk[j] = false;
-            act[j] = ballot(r.live) != 0;
-            zro[j] = ballot(r.live && anyzero) != 0;
-        }
+    for (int j = 0; j < NS; ++j) {
+        sidx[j] = j * 64 + lane;
+        const bool live = sidx[j] < N;
+        float sp[3];
+        zl[j] = ray_setup<DIM>(T, faces, q, live ? sidx[j] : 0, sp, iv[j]);
+        open[j] = __ballot(live);
+    }
 
-        // ---- corridor walk over the columns (all wave-uniform)
-        const float F0[3] = {T.c[0] - T.half[0], T.c[1] - T.half[1], T.c[2] - T.half[2]};
-        const float F1[3] = {T.c[0] + T.half[0], T.c[1] + T.half[1], T.c[2] + T.half[2]};
-        const int a = fabsf(T.c[0] - q[0]) >= fabsf(T.c[1] - q[1]) ? 0 : 1;
-        const int b = 1 - a;
-        const float ga = a == 0 ? X.x0 : X.y0, gb = a == 0 ? X.y0 : X.x0;
-        const int na = a == 0 ? X.nx : X.ny, nb = a == 0 ? X.ny : X.nx;
-        const float qa = q[a], qb = q[b], qz = q[2];
-        const float ua0 = F0[a] - qa, ua1 = F1[a] - qa;
-        const float iua0 = ua0 != 0.0f ? 1.0f / ua0 : 0.0f;
-        const float iua1 = ua1 != 0.0f ? 1.0f / ua1 : 0.0f;
-        const float vb0 = F0[b] - qb, vb1 = F1[b] - qb;
-        const float wz0 = F0[2] - qz;
-        const float amin = fminf(qa, F0[a]), amax = fmaxf(qa, F1[a]);
-        const float gend_a = ga + na * X.cs, gend_b = gb + nb * X.cs;
-        bool stop = !(amax >= ga && amin < gend_a);
-        int ia_lo = max(0, min(na - 1, (int)floorf((amin - ga) * X.inv_cs)));
-        int ia_hi = max(0, min(na - 1, (int)floorf((amax - ga) * X.inv_cs)));
-        const int step = (qa <= T.c[a]) ? -1 : 1;
-        int ia = step < 0 ? ia_hi : ia_lo;
-        const int ia_end = step < 0 ? ia_lo - 1 : ia_hi + 1;
-        for (; !stop && ia != ia_end; ia += step) {
-            const float A0 = ga + ia * X.cs, A1 = A0 + X.cs;
-            float l0 = 0.0f, l1 = 1.0f;
-            // rectangle (1-l) q + l F meets the slab [A0, A1] along axis a
-            const float r1 = A1 - qa, r2 = A0 - qa;
-            if (ua0 > 0.0f) l1 = fminf(l1, r1 * iua0);
-            else if (ua0 < 0.0f) l0 = fmaxf(l0, r1 * iua0);
-            else if (r1 < 0.0f) continue;
-            if (ua1 > 0.0f) l0 = fmaxf(l0, r2 * iua1);
-            else if (ua1 < 0.0f) l1 = fminf(l1, r2 * iua1);
-            else if (r2 > 0.0f) continue;
-            l0 = fmaxf(0.0f, l0 - kLambdaMargin);
-            l1 = fminf(1.0f, l1 + kLambdaMargin);
-            if (l0 > l1) continue;
-            const float bl = fminf(qb + l0 * vb0, qb + l1 * vb0) - kWalkMargin;
-            const float bh = fmaxf(qb + l0 * vb1, qb + l1 * vb1) + kWalkMargin;
-            if (bh < gb || bl >= gend_b) continue;
-            const float zf =
-                DIM == 3 ? fminf(qz + l0 * wz0, qz + l1 * wz0) - kWalkMargin : -INFINITY;
-            const int ib0 = max(0, min(nb - 1, (int)floorf((bl - gb) * X.inv_cs)));
-            const int ib1 = max(0, min(nb - 1, (int)floorf((bh - gb) * X.inv_cs)));
+    // ---- corridor walk (wave-uniform), slabs prepared 64 at a time
+    const float F0[3] = {T.c[0] - T.half[0], T.c[1] - T.half[1], T.c[2] - T.half[2]};
+    const float F1[3] = {T.c[0] + T.half[0], T.c[1] + T.half[1], T.c[2] + T.half[2]};
+    const int a = fabsf(T.c[0] - q[0]) >= fabsf(T.c[1] - q[1]) ? 0 : 1;
+    const int na = a == 0 ? X.nx : X.ny, nb = a == 0 ? X.ny : X.nx;
+    const float qa = a == 0 ? q[0] : q[1], qb = a == 0 ? q[1] : q[0], qz = q[2];
+    const float F0a = a == 0 ? F0[0] : F0[1], F1a = a == 0 ? F1[0] : F1[1];
+    const float F0b = a == 0 ? F0[1] : F0[0], F1b = a == 0 ? F1[1] : F1[0];
+    const float ca = a == 0 ? T.c[0] : T.c[1];
+    const float ua0 = F0a - qa, ua1 = F1a - qa;
+    const float iua0 = ua0 != 0.0f ? __builtin_amdgcn_rcpf(ua0) : 0.0f;
+    const float iua1 = ua1 != 0.0f ? __builtin_amdgcn_rcpf(ua1) : 0.0f;
+    const float vb0 = F0b - qb, vb1 = F1b - qb;
+    const float wz0 = F0[2] - qz, wz1 = F1[2] - qz;
+    const float amin = fminf(qa, F0a), amax = fmaxf(qa, F1a);
+    const float gend_a = na * X.cs, gend_b = nb * X.cs;
+    bool stop = !(amax >= 0.0f && amin < gend_a);
+    const int ia_lo = max(0, min(na - 1, (int)floorf(amin * X.inv_cs)));
+    const int ia_hi = max(0, min(na - 1, (int)floorf(amax * X.inv_cs)));
+    const int step = (qa <= ca) ? -1 : 1;
+    const int ia_first = step < 0 ? ia_hi : ia_lo;
+    const int n_slabs = ia_hi - ia_lo + 1;
+
+    for (int base = 0; !stop && base < n_slabs; base += 64) {
+        // lane l prepares slab base + l: the rectangles (1-l) q + l F meeting
+        // the slab [A0, A1] along axis a give the corridor's extent [bl, bh]
+        // along b and its lowest point zf there.
+        const int ia_l = ia_first + step * (base + lane);
+        bool ok = base + lane < n_slabs;
+        const float A0 = ia_l * X.cs, A1 = A0 + X.cs;
+        float l0 = 0.0f, l1 = 1.0f;
+        const float r1 = A1 - qa, r2 = A0 - qa;
+        if (ua0 > 0.0f) l1 = fminf(l1, r1 * iua0);
+        else if (ua0 < 0.0f) l0 = fmaxf(l0, r1 * iua0);
+        else ok = ok && r1 >= 0.0f;
+        if (ua1 > 0.0f) l0 = fmaxf(l0, r2 * iua1);
+        else if (ua1 < 0.0f) l1 = fminf(l1, r2 * iua1);
+        else ok = ok && r2 <= 0.0f;
+        l0 = fmaxf(0.0f, l0 - kLambdaMargin);
+        l1 = fminf(1.0f, l1 + kLambdaMargin);
+        ok = ok && l0 <= l1;
+        const float bl = fminf(qb + l0 * vb0, qb + l1 * vb0) - kWalkMargin;
+        const float bh = fmaxf(qb + l0 * vb1, qb + l1 * vb1) + kWalkMargin;
+        ok = ok && bh >= 0.0f && bl < gend_b;
+        const float zf = DIM == 3 ? fminf(qz + l0 * wz0, qz + l1 * wz0) - kWalkMargin : 0.0f;
+        const float zc = DIM == 3 ? fmaxf(qz + l0 * wz1, qz + l1 * wz1) + kWalkMargin : 0.0f;
+        const int ib0_l = max(0, min(nb - 1, (int)floorf(bl * X.inv_cs)));
+        const int ib1_l = max(0, min(nb - 1, (int)floorf(bh * X.inv_cs)));
+        // the corridor's slice as an x-y rectangle, in ordered-integer form
+        const unsigned ux0_l = ord(a == 0 ? A0 : bl), ux1_l = ord(a == 0 ? A1 : bh);
+        const unsigned uy0_l = ord(a == 0 ? bl : A0), uy1_l = ord(a == 0 ? bh : A1);
+        const unsigned zf_l = ord(zf), zc_l = DIM == 3 ? ord(zc) : 0xffffffffu;
+        unsigned long long todo = __ballot(ok);
+        while (!stop && todo) {
+            const int sl = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int ia = __builtin_amdgcn_readlane(ia_l, sl);
+            const int ib0 = __builtin_amdgcn_readlane(ib0_l, sl);
+            const int ib1 = __builtin_amdgcn_readlane(ib1_l, sl);
+            const unsigned ux0 = __builtin_amdgcn_readlane(ux0_l, sl);
+            const unsigned ux1 = __builtin_amdgcn_readlane(ux1_l, sl);
+            const unsigned uy0 = __builtin_amdgcn_readlane(uy0_l, sl);
+            const unsigned uy1 = __builtin_amdgcn_readlane(uy1_l, sl);
+            const unsigned uzf = __builtin_amdgcn_readlane(zf_l, sl);
+            const unsigned uzc = __builtin_amdgcn_readlane(zc_l, sl);
             for (int ib = ib0; !stop && ib <= ib1; ++ib) {
                 const int col = a == 0 ? ia + X.nx * ib : ib + X.nx * ia;
-                const int rb = X.col_start[col], re = X.col_start[col + 1];
-                if (STATS) ++n_cols;
+                const int rb = col_start[col], re = col_start[col + 1];
+                if (STATS) ++ws.cols;
                 for (int rr = rb; rr < re; ++rr) {
-                    const BoxRec B = X.recs[rr];
-                    if (DIM == 3 && B.hi[2] < zf) break;
-                    float lq[3], hq[3];
+                    const BoxRec B = recs[rr];
+                    // below the corridor's lowest point (so is the rest of the
+                    // list), or beside or above its slice: cannot meet its rays
+                    const bool low = DIM == 3 && __float_as_uint(B.hi[2]) < uzf;
+                    const bool beside =
+                        __float_as_uint(B.hi[0]) < ux0 || __float_as_uint(B.lo[0]) > ux1 ||
+                        __float_as_uint(B.hi[1]) < uy0 || __float_as_uint(B.lo[1]) > uy1 ||
+                        (DIM == 3 && __float_as_uint(B.lo[2]) > uzc);
+                    if (low || beside) {
+                        if (low) break;
+                        continue;
+                    }
+                    float blq[3], bhq[3];
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        lq[k] = B.lo[k] - q[k];
-                        hq[k] = B.hi[k] - q[k];
+                        blq[k] = B.lo[k] - q[k];
+                        bhq[k] = B.hi[k] - q[k];
                     }
-                    bool any_blk = false, any_act = false;
+                    unsigned long long hit_any = 0, open_any = 0;
 #pragma unroll
                     for (int j = 0; j < NS; ++j) {
-                        if (!act[j]) continue;
-                        Ray &r = ray[j];
-                        const bool need = r.live && !blk[j];
-                        bool hit;
+                        if (!open[j]) continue;
+                        unsigned long long hit, unsure;
+                        float gap = 0.0f;
                         if (EXACT64) {
-                            hit = need && exact_contact<DIM>(q, r.s, B);
-                            if (STATS) n_tests += __popcll(ballot(need));
+                            hit = 0;
+                            unsure = open[j];
                         } else {
-                            const float gap = zro[j] ? slab_gap<DIM, true>(r, lq, hq)
-                                                     : slab_gap<DIM, false>(r, lq, hq);
-                            const bool unsure = need && (P.recheck_all || fabsf(gap) <= P.eps);
-                            hit = need && gap > P.eps;
-                            if (unsure) {
-                                const bool ex = exact_contact<DIM>(q, r.s, B);
-                                if (STATS && P.recheck_all) {
-                                    // float32 decision with the default margin
-                                    const bool decided = fabsf(gap) > 0x1p-20f;
-                                    if (decided && ((gap > 0.0f) != ex)) ++n_disagree;
-                                }
-                                hit = ex;
-                            }
-                            if (STATS) {
-                                n_tests += __popcll(ballot(need));
-                                n_rechecks += __popcll(ballot(unsure));
-                            }
+                            // eps = +inf sends every test to the exact predicate
+                            gap = slab_gap<DIM>(iv[j], blq, bhq);
+                            hit = __ballot(gap > P.eps) & open[j];
+                            unsure = __ballot(fabsf(gap) <= P.eps || zl[j]) & open[j];
                         }
-                        blk[j] = blk[j] || hit;
-                        const bool open = r.live && !blk[j];
-                        act[j] = ballot(open) != 0;
-                        any_act = any_act || act[j];
-                        any_blk = any_blk || (ballot(blk[j]) != 0);
+                        if (__builtin_expect(unsure != 0, 0)) {
+                            bool ex = false;
+                            if ((unsure >> lane) & 1) {
+                                float sp[3], d[3];
+                                // opaque copy: keeps this rare work out of the
+                                // hot loops (it is loop-invariant per ray)
+                                int si = sidx[j];
+                                asm volatile("" : "+v"(si));
+                                sample_pos<DIM>(T, faces, si, sp);
+                                float lq2[3], hq2[3];
+#pragma unroll
+                                for (int k = 0; k < 3; ++k) {
+                                    d[k] = sp[k] - q[k];
+                                    // keep this rare path's work inside the branch
+                                    lq2[k] = blq[k];
+                                    hq2[k] = bhq[k];
+                                    asm volatile("" : "+v"(lq2[k]), "+v"(hq2[k]));
+                                }
+                                ex = exact_contact<DIM>(d, lq2, hq2);
+                                if (STATS && !EXACT64 && !zl[j] && fabsf(gap) > P.eps_ref &&
+                                    (gap > 0.0f) != ex)
+                                    ++n_disagree;
+                            }
+                            hit = (hit & ~unsure) | (__ballot(ex) & unsure);
+                        }
+                        if (STATS) {
+                            ws.tests += __popcll(open[j]);
+                            ws.rechecks += EXACT64 ? 0 : __popcll(unsure);
+                            ++ws.slots;
+                        }
+                        open[j] &= ~hit;
+                        hit_any |= hit;
+                        open_any |= open[j];
                     }
-                    if (P.mode == VCM_FULL ? any_blk : !any_act) {
+                    if (MODE == VCM_FULL ? hit_any != 0 : open_any == 0) {
                         stop = true;
                         break;
                     }
                 }
+                // FRACTION mode: pack the unresolved rays into fewer slots
+                if (NS > 1 && MODE == VCM_FRACTION && !stop) {
+                    int tot = 0, used = 0;
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) {
+                        tot += __popcll(open[j]);
+                        used += open[j] != 0;
+                    }
+                    if (((tot + 63) >> 6) < used) {
+                        int pos = 0;
+#pragma unroll
+                        for (int j = 0; j < NS; ++j) {
+                            if ((open[j] >> lane) & 1) lds[pos + mbcnt(open[j])] = sidx[j];
+                            pos += __popcll(open[j]);
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                        for (int j = 0; j < NS; ++j) {
+                            const bool live = j * 64 + lane < tot;
+                            sidx[j] = live ? lds[j * 64 + lane] : 0;
+                            float sp[3];
+                            zl[j] = ray_setup<DIM>(T, faces, q, sidx[j], sp, iv[j]);
+                            open[j] = __ballot(live);
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
             }
         }
+    }
+    int vis = 0;
 #pragma unroll
-        for (int j = 0; j < NS; ++j) visible += __popcll(ballot(ray[j].live && !blk[j]));
-    }
+    for (int j = 0; j < NS; ++j) vis += __popcll(open[j]);
+    return vis;
+}
 
-    // ---- colour, bin, outputs
-    int cnt;
-    R col;
-    if (!fov || N == 0) {
-        cnt = 0;
-        col = R(0);
-    } else if (P.mode == VCM_FRACTION) {
-        cnt = visible;
-        col = (R(visible) / R(N)) * craw;
-    } else {
-        cnt = visible == N ? N : 0;
-        col = visible == N ? craw : R(0);
-    }
-    R cb = col;
-    if (P.bin_scale == VCM_BIN_LOG) {
-        const R veff = col * R(P.V0);
-        cb = veff <= R(P.mu) ? R(0) : fmin(R(1), log(veff / R(P.mu)) * R(P.inv_log_V0_mu));
-    }
-    const int bn = min(P.n_bins - 1, static_cast<int>(floor(cb * R(P.n_bins))));
-    if (lane == 0) {
-        A.bin[vp] = static_cast<uint8_t>(bn);
-        if (A.c) A.c[vp] = static_cast<float>(col);
-        if (A.count) A.count[vp] = static_cast<uint16_t>(cnt);
-        if (STATS) {
-            atomicAdd(&A.stats->rays, (unsigned long long)((fov && N > 0) ? N : 0));
-            atomicAdd(&A.stats->box_tests, n_tests);
-            atomicAdd(&A.stats->rechecks, n_rechecks);
-            atomicAdd(&A.stats->columns, n_cols);
+constexpr int kChunk = 8;  // consecutive viewpoints of one grid row per work item
+
+// Persistent wavefronts take work items (kChunk viewpoints of one row) from a
+// device counter; each viewpoint is traced by the whole wavefront, and the
+// chunk's results are written by kChunk lanes at once.
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_brute(BruteArgs A, const int32_t *col_start_g,
+                                               const BoxRec *recs_g) {
+    // same kernel symbol in both compiler passes; constant-space view inside
+    const cptr_i32 col_start = (cptr_i32)col_start_g;
+    const cptr_rec recs = (cptr_rec)recs_g;
+    using R = typename std::conditional<EXACT64, double, float>::type;
+    __shared__ int lds_rays[4][kMaxSamples];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int *lds = lds_rays[wave];
+    const TargetDesc &T = A.tgt;
+    const ParamDesc &P = A.prm;
+    const int n0 = A.grid.n[0], n1 = A.grid.n[1];
+    const int cpr = (n0 + kChunk - 1) / kChunk;
+    WaveStats ws;
+    unsigned long long n_disagree = 0;
+
+    for (;;) {
+        unsigned item = 0;
+        if (lane == 0) item = atomicAdd(A.counter, 1u);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
+        if (item >= A.n_items) break;
+        const int row = static_cast<int>(item / static_cast<unsigned>(cpr));
+        const int x0 = static_cast<int>(item - static_cast<unsigned>(row) * cpr) * kChunk;
+        const int jj = row % n1, kk = A.k_begin + row / n1;
+        const int nv = min(kChunk, n0 - x0);
+        const int64_t v0 = x0 + static_cast<int64_t>(n0) * (jj + static_cast<int64_t>(n1) * kk);
+        uint8_t o_bin = 0;
+        float o_c = 0.0f;
+        uint16_t o_cnt = 0;
+        for (int t = 0; t < nv; ++t) {
+            const int ii[3] = {x0 + t, jj, kk};
+            float q[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                q[k] = (k < DIM) ? A.grid.o[k] + static_cast<float>(2 * ii[k] + 1) * A.grid.h2[k] : 0.0f;
+            // live facets packed 4 bits each: cube faces whose outer side
+            // contains q strictly (code 2k+1 for +k, 2k for -k)
+            unsigned faces = 0;
+            int nf = 0;
+            if (T.kind == VCM_CUBE) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const bool up = q[k] > T.c[k] + T.half[k];
+                    const bool dn = q[k] < T.c[k] - T.half[k];
+                    if (up || dn) {
+                        faces |= static_cast<unsigned>(2 * k + (up ? 1 : 0)) << (4 * nf);
+                        ++nf;
+                    }
+                }
+            } else {
+                nf = 1;
+            }
+            const int N = nf * T.per_facet;
+            const bool fov = in_fov<DIM>(T, P, q);
+            int cnt = 0;
+            R col = R(0);
+            if (fov && N > 0) {
+                if (STATS) ws.rays += N;
+                const int vis =
+                    trace_viewpoint<DIM, NS, EXACT64, MODE, STATS>(A, col_start, recs, q, faces, N, lds, ws,
+                                                                    n_disagree);
+                if (MODE == VCM_FRACTION) {
+                    cnt = vis;
+                    if (vis > 0) col = (R(vis) / R(N)) * raw_colour<DIM, R>(T, P, q);
+                } else if (vis == N) {
+                    cnt = N;
+                    col = raw_colour<DIM, R>(T, P, q);
+                }
+            }
+            R cb = col;
+            if (P.bin_scale == VCM_BIN_LOG) {
+                const R veff = col * R(P.V0);
+                cb = veff <= R(P.mu) ? R(0) : fmin(R(1), log(veff / R(P.mu)) * R(P.inv_log_V0_mu));
+            }
+            const int bn = min(P.n_bins - 1, static_cast<int>(floor(cb * R(P.n_bins))));
+            if (lane == t) {
+                o_bin = static_cast<uint8_t>(bn);
+                o_c = static_cast<float>(col);
+                o_cnt = static_cast<uint16_t>(cnt);
+            }
+        }
+        if (lane < nv) {
+            A.bin[v0 + lane] = o_bin;
+            if (A.c) A.c[v0 + lane] = o_c;
+            if (A.count) A.count[v0 + lane] = o_cnt;
         }
     }
-    if (STATS && n_disagree) atomicAdd(&A.stats->fp32_disagree, n_disagree);  // per lane
+    if (STATS) {
+        if (lane == 0) {
+            atomicAdd(&A.stats->rays, ws.rays);
+            atomicAdd(&A.stats->box_tests, ws.tests);
+            atomicAdd(&A.stats->slot_tests, ws.slots);
+            atomicAdd(&A.stats->rechecks, ws.rechecks);
+            atomicAdd(&A.stats->columns, ws.cols);
+            atomicAdd(&A.stats->inside_box, ws.inside);
+        }
+        if (n_disagree) atomicAdd(&A.stats->fp32_disagree, n_disagree);  // per lane
+    }
+}
+
+__global__ void k_zero_counter(unsigned *c) {
+    if (threadIdx.x == 0) *c = 0u;
+}
+
+struct Launch {
+    dim3 grid;
+    bool stats;
+    hipStream_t st;
+};
+
+template <int DIM, int NS, bool EXACT64, int MODE>
+void launch_mode(const BruteArgs &a, const Launch &L) {
+    if (L.stats)
+        hipLaunchKernelGGL((k_brute<DIM, NS, EXACT64, MODE, true>), L.grid, dim3(256), 0, L.st, a,
+                           a.idx.col_start, a.idx.recs);
+    else
+        hipLaunchKernelGGL((k_brute<DIM, NS, EXACT64, MODE, false>), L.grid, dim3(256), 0, L.st, a,
+                           a.idx.col_start, a.idx.recs);
 }
 
 template <int DIM, int NS, bool EXACT64>
-void launch_ns(const BruteArgs &a, bool stats, dim3 grid, hipStream_t st) {
-    if (stats)
-        hipLaunchKernelGGL((k_brute<DIM, NS, EXACT64, true>), grid, dim3(256), 0, st, a);
+void launch_ns(const BruteArgs &a, const Launch &L) {
+    if (a.prm.mode == VCM_FULL)
+        launch_mode<DIM, NS, EXACT64, VCM_FULL>(a, L);
     else
-        hipLaunchKernelGGL((k_brute<DIM, NS, EXACT64, false>), grid, dim3(256), 0, st, a);
+        launch_mode<DIM, NS, EXACT64, VCM_FRACTION>(a, L);
 }
 
 template <int DIM, bool EXACT64>
-void launch_dim(const BruteArgs &a, int ns, bool stats, dim3 grid, hipStream_t st) {
+void launch_dim(const BruteArgs &a, int ns, const Launch &L) {
     switch (ns) {
-        case 1: launch_ns<DIM, 1, EXACT64>(a, stats, grid, st); break;
-        case 2: launch_ns<DIM, 2, EXACT64>(a, stats, grid, st); break;
-        case 3: launch_ns<DIM, 3, EXACT64>(a, stats, grid, st); break;
-        case 4: launch_ns<DIM, 4, EXACT64>(a, stats, grid, st); break;
-        case 5: launch_ns<DIM, 5, EXACT64>(a, stats, grid, st); break;
-        default: launch_ns<DIM, 6, EXACT64>(a, stats, grid, st); break;
+        case 1: launch_ns<DIM, 1, EXACT64>(a, L); break;
+        case 2: launch_ns<DIM, 2, EXACT64>(a, L); break;
+        case 3: launch_ns<DIM, 3, EXACT64>(a, L); break;
+        case 4: launch_ns<DIM, 4, EXACT64>(a, L); break;
+        case 5: launch_ns<DIM, 5, EXACT64>(a, L); break;
+        default: launch_ns<DIM, 6, EXACT64>(a, L); break;
     }
+}
+
+int device_cus(int device) {
+    static int cached[64] = {0};
+    if (device < 0 || device >= 64) return 256;
+    if (!cached[device]) {
+        hipDeviceProp_t prop;
+        cached[device] = (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+                             ? prop.multiProcessorCount
+                             : 256;
+    }
+    return cached[device];
 }
 
 }  // namespace
 
 vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g,
-                        const ParamDesc &p, const vcm_result &r, int64_t vp_begin,
-                        int64_t vp_end, hipStream_t stream, DevStats *stats) {
-    if (vp_end <= vp_begin) return VCM_OK;
+                        const ParamDesc &p, const vcm_result &r, hipStream_t stream,
+                        DevStats *stats) {
+    if (g.count <= 0) return VCM_OK;
     BruteArgs a{};
     a.idx = ix.dev;
     a.tgt = t;
@@ -412,28 +620,42 @@ vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g,
     a.c = r.c;
     a.count = r.count;
     a.stats = stats;
-    a.vp_begin = vp_begin;
-    a.vp_end = vp_end;
     const int max_n = t.per_facet * (t.kind == VCM_CUBE ? 3 : 1);
     const int ns = (max_n + 63) / 64;
     if (ns < 1 || ns > kMaxSlots) return set_error(VCM_E_INVALID, "too many target samples");
-    const int64_t nblk = (vp_end - vp_begin + 3) / 4;
-    if (nblk > 0x7fffffff) return set_error(VCM_E_INVALID, "too many viewpoints for one launch");
-    dim3 grid(static_cast<unsigned>(nblk));
-    const bool st = stats != nullptr;
-    if (ix.dim == 2) {
-        if (p.fp64)
-            launch_dim<2, true>(a, ns, st, grid, stream);
-        else
-            launch_dim<2, false>(a, ns, st, grid, stream);
-    } else {
-        if (p.fp64)
-            launch_dim<3, true>(a, ns, st, grid, stream);
-        else
-            launch_dim<3, false>(a, ns, st, grid, stream);
+    unsigned *counter = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&counter), sizeof(unsigned), stream);
+    if (e != hipSuccess) return set_error(VCM_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    a.counter = counter;
+    Launch L;
+    L.stats = stats != nullptr;
+    L.st = stream;
+    const int64_t cpr = (g.n[0] + kChunk - 1) / kChunk;
+    const int64_t rows_per_layer = g.n[1];
+    // launches over z slabs keep the work-item count within 32 bits
+    const int64_t max_layers = std::max<int64_t>(1, (int64_t(1) << 30) / (cpr * rows_per_layer));
+    const int cus = device_cus(ix.device);
+    for (int64_t k0 = 0; k0 < g.n[2]; k0 += max_layers) {
+        const int64_t nl = std::min<int64_t>(max_layers, g.n[2] - k0);
+        a.k_begin = static_cast<int32_t>(k0);
+        a.n_items = static_cast<unsigned>(cpr * rows_per_layer * nl);
+        const int64_t blocks = std::min<int64_t>((a.n_items + 3) / 4, int64_t(cus) * 8);
+        L.grid = dim3(static_cast<unsigned>(blocks));
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, counter);
+        if (ix.dim == 2) {
+            if (p.fp64) launch_dim<2, true>(a, ns, L);
+            else launch_dim<2, false>(a, ns, L);
+        } else {
+            if (p.fp64) launch_dim<3, true>(a, ns, L);
+            else launch_dim<3, false>(a, ns, L);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) {
+            hipFreeAsync(counter, stream);
+            return set_error(VCM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+        }
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return set_error(VCM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    hipFreeAsync(counter, stream);
     return VCM_OK;
 }
 

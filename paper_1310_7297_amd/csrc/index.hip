@@ -17,7 +17,8 @@ namespace vcm {
 namespace {
 
 struct BuildGrid {
-    float x0, y0, inv_cs;
+    float fx, fy, fz;  // frame origin (boxes are stored relative to it)
+    float inv_cs;
     int32_t nx, ny;
 };
 
@@ -36,8 +37,8 @@ __global__ void k_count(const float *__restrict__ lo, const float *__restrict__ 
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t ax, bx, ay, by;
-    footprint_cols(lo[i], hi[i], g.x0, g.inv_cs, g.nx, ax, bx);
-    footprint_cols(lo[n + i], hi[n + i], g.y0, g.inv_cs, g.ny, ay, by);
+    footprint_cols(lo[i] - g.fx, hi[i] - g.fx, 0.0f, g.inv_cs, g.nx, ax, bx);
+    footprint_cols(lo[n + i] - g.fy, hi[n + i] - g.fy, 0.0f, g.inv_cs, g.ny, ay, by);
     for (int32_t y = ay; y <= by; ++y)
         for (int32_t x = ax; x <= bx; ++x) atomicAdd(&counts[y * g.nx + x], 1);
 }
@@ -74,15 +75,17 @@ __global__ void k_fill(const float *__restrict__ lo, const float *__restrict__ h
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     BoxRec r;
+    const float f[3] = {g.fx, g.fy, g.fz};
     for (int k = 0; k < 3; ++k) {
-        r.lo[k] = (k < dim) ? lo[k * n + i] : -INFINITY;
-        r.hi[k] = (k < dim) ? hi[k * n + i] : INFINITY;
+        // exact: both terms are multiples of 2^-8 and the result is below 2^15
+        r.lo[k] = (k < dim) ? lo[k * n + i] - f[k] : 0.0f;
+        r.hi[k] = (k < dim) ? hi[k * n + i] - f[k] : INFINITY;
     }
     r.id = static_cast<int32_t>(i);
     r.pad = 0;
     int32_t ax, bx, ay, by;
-    footprint_cols(r.lo[0], r.hi[0], g.x0, g.inv_cs, g.nx, ax, bx);
-    footprint_cols(r.lo[1], r.hi[1], g.y0, g.inv_cs, g.ny, ay, by);
+    footprint_cols(r.lo[0], r.hi[0], 0.0f, g.inv_cs, g.nx, ax, bx);
+    footprint_cols(r.lo[1], r.hi[1], 0.0f, g.inv_cs, g.ny, ay, by);
     for (int32_t y = ay; y <= by; ++y)
         for (int32_t x = ax; x <= bx; ++x) {
             int32_t slot = atomicAdd(&cursor[y * g.nx + x], 1);
@@ -125,7 +128,7 @@ vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, i
                               double cell_size, hipStream_t stream) {
     auto t0 = std::chrono::steady_clock::now();
     // Column grid over the grown footprints.
-    double mnx = 0, mny = 0, mxx = 0, mxy = 0;
+    double mnx = 0, mny = 0, mxx = 0, mxy = 0, mnz = 0;
     if (n > 0) {
         mnx = mny = 1e30;
         mxx = mxy = -1e30;
@@ -134,6 +137,7 @@ vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, i
             mny = std::min(mny, (double)h_lo[n + i]);
             mxx = std::max(mxx, (double)h_hi[i]);
             mxy = std::max(mxy, (double)h_hi[n + i]);
+            if (ix->dim == 3) mnz = std::min(mnz, (double)h_lo[2 * n + i]);
         }
     }
     double cs = cell_size;
@@ -158,7 +162,7 @@ vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, i
         ny = (int64_t)std::floor((mxy + kFatMargin - y0) / cs) + 1;
     }
     const int32_t ncols = (int32_t)(nx * ny);
-    BuildGrid g{(float)x0, (float)y0, (float)(1.0 / cs), (int32_t)nx, (int32_t)ny};
+    BuildGrid g{(float)x0, (float)y0, (float)mnz, (float)(1.0 / cs), (int32_t)nx, (int32_t)ny};
 
     float *d_lo = nullptr, *d_hi = nullptr;
     int32_t *d_counts = nullptr, *d_cursor = nullptr;
@@ -184,13 +188,14 @@ vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, i
                            hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     HIP_TRY(hipMalloc(&ix->d_recs, sizeof(BoxRec) * std::max(total, 1)));
+    BoxRec *d_recs = ix->d_recs;
     HIP_TRY(hipMemcpyAsync(d_cursor, ix->d_col_start, sizeof(int32_t) * ncols,
                            hipMemcpyDeviceToDevice, stream));
     if (n > 0)
         hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + T - 1) / T)), dim3(T), 0, stream, d_lo,
-                           d_hi, n, ix->dim, g, d_cursor, ix->d_recs);
+                           d_hi, n, ix->dim, g, d_cursor, d_recs);
     hipLaunchKernelGGL(k_sort, dim3((unsigned)((ncols + T - 1) / T)), dim3(T), 0, stream,
-                       ix->d_col_start, ncols, ix->d_recs);
+                       ix->d_col_start, ncols, d_recs);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(stream));
     hipFree(d_lo);
@@ -202,8 +207,11 @@ vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, i
     ix->n_refs = total;
     ix->dev.col_start = ix->d_col_start;
     ix->dev.recs = ix->d_recs;
-    ix->dev.x0 = (float)x0;
-    ix->dev.y0 = (float)y0;
+    ix->frame[0] = x0;
+    ix->frame[1] = y0;
+    ix->frame[2] = ix->dim == 3 ? mnz : 0.0;
+    ix->dev.x0 = 0.0f;
+    ix->dev.y0 = 0.0f;
     ix->dev.cs = (float)cs;
     ix->dev.inv_cs = (float)(1.0 / cs);
     ix->dev.nx = (int32_t)nx;

@@ -20,6 +20,8 @@ constexpr int kMaxSamples = 384;
 constexpr int kMaxSlots = 6;
 
 // One box reference inside a column list (32 bytes, one scalar load).
+// Coordinates are in the index frame (see DevIndex), where they are >= 0,
+// so two of them compare like their bit patterns as unsigned integers.
 struct alignas(32) BoxRec {
     float lo[3];
     float hi[3];
@@ -28,10 +30,12 @@ struct alignas(32) BoxRec {
 };
 
 // Device view of the obstacle index.
+// The index frame is the scene translated by -frame (an exact dyadic
+// offset): the column grid starts at (0, 0) and every box has z >= 0.
 struct DevIndex {
     const int32_t *col_start;  // nx*ny + 1 offsets into recs
     const BoxRec *recs;        // column lists, each sorted by decreasing hi.z
-    float x0, y0;              // grid origin (multiples of the cell size)
+    float x0, y0;              // grid origin in the frame (0, 0)
     float cs, inv_cs;          // cell size (a power of two) and its inverse
     int32_t nx, ny;
     int32_t dim;
@@ -45,6 +49,8 @@ struct TargetDesc {
     int32_t nsign;
     int32_t su, sv;     // lattice per facet
     int32_t per_facet;  // su * sv
+    uint64_t m_pf;      // ceil(2^32 / per_facet): exact division of sample indices
+    uint64_t m_su;      // ceil(2^32 / su)
     float c[3];         // centre
     float half[3];      // half extents of the target's bounding box
     float hu, hv;       // half lattice spacing along u and v
@@ -74,8 +80,8 @@ struct ParamDesc {
     float inv_V0;
     float mu;           // angular resolution, radians
     float inv_log_V0_mu;
-    float eps;          // slab-test margin
-    int32_t recheck_all;
+    float eps;          // slab-test margin (+inf: every test exact)
+    float eps_ref;      // the default margin (disagreement statistics)
     int32_t fp64;       // every ray test exact in float64, measure in float64
 };
 
@@ -86,7 +92,9 @@ struct DevStats {
     unsigned long long rechecks;
     unsigned long long fp32_disagree;
     unsigned long long columns;
-    unsigned long long pad[3];
+    unsigned long long slot_tests;
+    unsigned long long inside_box;
+    unsigned long long pad;
 };
 
 // Everything one brute-force launch needs (passed by value).
@@ -99,8 +107,9 @@ struct BruteArgs {
     float *c;
     uint16_t *count;
     DevStats *stats;
-    int64_t vp_begin;   // first viewpoint of this launch
-    int64_t vp_end;
+    unsigned *counter;  // work-item counter (zeroed before the launch)
+    int32_t k_begin;    // first z layer of this launch
+    uint32_t n_items;   // work items in this launch
 };
 
 // Host-side index object behind the opaque vcm_index handle.
@@ -112,6 +121,7 @@ struct Index {
     DevIndex dev{};
     int32_t *d_col_start = nullptr;
     BoxRec *d_recs = nullptr;
+    double frame[3] = {0, 0, 0};  // world coordinates of the frame origin
     size_t bytes = 0;
     double build_ms = 0.0;
     // Host copy of the boxes (float32, exact), used for validation.
@@ -128,8 +138,8 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
 
 // Launch the brute-force kernel over [vp_begin, vp_end) on `stream`.
 vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g,
-                        const ParamDesc &p, const vcm_result &r, int64_t vp_begin,
-                        int64_t vp_end, hipStream_t stream, DevStats *stats);
+                        const ParamDesc &p, const vcm_result &r, hipStream_t stream,
+                        DevStats *stats);
 
 // Build the column index on the device.
 vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, int64_t n,

@@ -48,3 +48,19 @@ def test_build_index_rejects(bad):
         vcm.vcm_build_index(scenes.Scene(dim, lo, hi))
     assert e.value.status == vcm.VCM_E_INVALID
     assert vcm.vcm_last_error()
+
+
+def test_every_kernel_stub_has_device_code():
+    """Each kernel the host side can launch has a device symbol of the same
+    name in the embedded gfx950 code object (a mismatch aborts at launch)."""
+    import re as _re
+    data = open(vcm.LIB_PATH, "rb").read()
+    stubs = set(m.decode() for m in _re.findall(rb"__device_stub__(\w+)", data))
+    assert stubs
+    # mangled stub names embed the kernel name after the namespace prefix
+    names = set()
+    for s in stubs:
+        names.add(s)
+    syms = set(m.decode() for m in _re.findall(rb"(_Z\w+)\.kd", data))
+    for s in names:
+        assert any(s in k for k in syms), s
