@@ -178,3 +178,132 @@ def viewpoint_coords(grid, vp_index) -> np.ndarray:
             continue
         out[:, a] = grid.origin[a] + (2 * ii[a] + 1) * (grid.extent[a] / (2.0 * grid.n[a]))
     return out
+
+
+# ------------------------------------------------------------ pruned -------
+
+class VoCells(ctypes.Structure):
+    _fields_ = [("nring", ctypes.c_int), ("d", ctypes.POINTER(ctypes.c_double)),
+                ("boff", ctypes.POINTER(ctypes.c_int64)), ("gam", ctypes.POINTER(ctypes.c_double)),
+                ("S", ctypes.c_double), ("mu", ctypes.c_double), ("d0", ctypes.c_double),
+                ("V0", ctypes.c_double)]
+
+
+def _plib():
+    L = lib()
+    if not hasattr(L, "_pruned_ready"):
+        L.vo_partition.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.POINTER(VoCells)]
+        L.vo_partition.restype = ctypes.c_int
+        L.vo_free_cells.argtypes = [ctypes.POINTER(VoCells)]
+        L.vo_cells_size.argtypes = [ctypes.POINTER(VoCells), ctypes.POINTER(ctypes.c_int64)]
+        L.vo_cells_size.restype = ctypes.c_int
+        L.vo_cells_copy.argtypes = [ctypes.POINTER(VoCells), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+        L.vo_pruned_colours.argtypes = [ctypes.POINTER(VoCells), ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.vo_meridian.argtypes = [ctypes.POINTER(VoTarget), ctypes.c_void_p, ctypes.c_void_p]
+        L.vo_block_rep.argtypes = [ctypes.POINTER(VoGrid), ctypes.c_int, ctypes.c_int, ctypes.c_int64]
+        L.vo_block_rep.restype = ctypes.c_int64
+        L.vo_eval_pruned.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.POINTER(VoTarget), ctypes.POINTER(VoGrid),
+                                     ctypes.POINTER(VoParams), ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.vo_eval_pruned.restype = ctypes.c_int
+        L.vo_map_error.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                   ctypes.c_void_p, ctypes.c_void_p]
+        L.vo_error_bounds.argtypes = [ctypes.POINTER(VoCells), ctypes.c_int, ctypes.c_void_p]
+        L._pruned_ready = True
+    return L
+
+
+class Cells:
+    """Equi-visible cells (rings x bands) of a target of size S."""
+
+    def __init__(self, S: float, mu_rad: float, d0: float):
+        self._c = VoCells()
+        if _plib().vo_partition(float(S), float(mu_rad), float(d0), ctypes.byref(self._c)):
+            raise ValueError("invalid partition parameters")
+        nb = ctypes.c_int64()
+        nr = _plib().vo_cells_size(ctypes.byref(self._c), ctypes.byref(nb))
+        self.d = np.zeros(nr + 1)
+        self.boff = np.zeros(nr + 1, dtype=np.int64)
+        self.gam = np.zeros(nb.value)
+        _plib().vo_cells_copy(ctypes.byref(self._c), self.d.ctypes.data, self.boff.ctypes.data,
+                              self.gam.ctypes.data)
+        self.S, self.mu, self.d0, self.V0 = self._c.S, self._c.mu, self._c.d0, self._c.V0
+
+    @property
+    def nring(self):
+        return len(self.d) - 1
+
+    def bands(self, i):
+        return self.gam[self.boff[i]:self.boff[i + 1]]
+
+    def colours(self, D: float, alpha: float):
+        out = np.zeros(3)
+        cell = np.zeros(2, dtype=np.int32)
+        tf = ctypes.c_int()
+        _plib().vo_pruned_colours(ctypes.byref(self._c), float(D), float(alpha), out.ctypes.data,
+                                  cell.ctypes.data, ctypes.addressof(tf))
+        return {"E": out[0], "M": out[1], "T": out[2], "ring": int(cell[0]), "band": int(cell[1]),
+                "t_fallback": bool(tf.value)}
+
+    def error_bounds(self, dim: int):
+        out = np.zeros(2)
+        _plib().vo_error_bounds(ctypes.byref(self._c), int(dim), out.ctypes.data)
+        return {"mbr": out[0], "tangent": out[1]}
+
+    def __del__(self):
+        try:
+            _plib().vo_free_cells(ctypes.byref(self._c))
+        except Exception:
+            pass
+
+
+def meridian(target, q):
+    T = make_target(target)
+    q = _vec3(q)
+    out = np.zeros(2)
+    _plib().vo_meridian(ctypes.byref(T), q.ctypes.data, out.ctypes.data)
+    return out[0], out[1]
+
+
+def block_rep(grid, dim, theta, idx):
+    G = make_grid(grid)
+    return int(_plib().vo_block_rep(ctypes.byref(G), int(dim), int(theta), int(idx)))
+
+
+def vcm_eval_pruned(scene, query, method: int, theta: int = 1,
+                    vp_index: Optional[np.ndarray] = None, nthreads: int = 1):
+    g = query.grid
+    if vp_index is None:
+        vp_index = np.arange(g.count, dtype=np.int64)
+    vp = np.ascontiguousarray(vp_index, dtype=np.int64)
+    n = len(vp)
+    lo = np.ascontiguousarray(scene.lo, dtype=np.float64)
+    hi = np.ascontiguousarray(scene.hi, dtype=np.float64)
+    T, G, P = make_target(query.target), make_grid(g), make_params(query.params)
+    out = {"count": np.zeros(n, dtype=np.uint16), "c": np.zeros(n), "cb": np.zeros(n),
+           "bin": np.zeros(n, dtype=np.uint8), "cell": np.zeros((n, 2), dtype=np.int32),
+           "t_fallback": np.zeros(n, dtype=np.uint8)}
+    r = _plib().vo_eval_pruned(int(scene.dim), int(scene.n), lo.ctypes.data, hi.ctypes.data,
+                               ctypes.byref(T), ctypes.byref(G), ctypes.byref(P), int(method),
+                               int(theta), vp.ctypes.data, n, int(nthreads),
+                               out["count"].ctypes.data, out["c"].ctypes.data,
+                               out["cb"].ctypes.data, out["bin"].ctypes.data,
+                               out["cell"].ctypes.data, out["t_fallback"].ctypes.data)
+    if r != 0:
+        raise ValueError("oracle rejected the pruned query")
+    return out
+
+
+def map_error(c_exact, c_approx):
+    ce = np.ascontiguousarray(c_exact, dtype=np.float64)
+    ca = np.ascontiguousarray(c_approx, dtype=np.float64)
+    s, a = ctypes.c_double(), ctypes.c_double()
+    _plib().vo_map_error(ce.ctypes.data, ca.ctypes.data, len(ce), ctypes.addressof(s),
+                         ctypes.addressof(a))
+    return s.value, a.value

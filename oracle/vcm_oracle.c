@@ -486,3 +486,392 @@ int vo_eval(int dim, int64_t nbox, const double *lo, const double *hi,
     free(bhi);
     return 0;
 }
+
+/* ===================================================================== */
+/* Pruned construction: equi-visible cells (Sec. III-A), MBR and tangent  */
+/* approximations (Sec. IV-A), error metric (Sec. V-A).                   */
+/* ===================================================================== */
+
+typedef struct {
+    int nring;          /* rings i = 0 .. nring-1                              */
+    double *d;          /* d[0..nring]: ring i is [d[i], d[i+1]); d[nring] = d_max */
+    int64_t *boff;      /* boff[0..nring]: bands of ring i are gam[boff[i] .. boff[i+1]-1] */
+    double *gam;        /* per ring: gamma_0 = pi/2 > gamma_1 > ... > gamma_{L+1} = 0 (radians);
+                           band j of the ring is (gamma_{j+1}, gamma_j]                   */
+    double S, mu, d0, V0;
+} vo_cells;
+
+/* Distance-based partition (Sec. III-A-1) followed by the angle-based
+ * partition of every ring (Sec. III-A-2), in the paper's order.
+ *
+ * Rings: starting at the near point d0 with V0 = 2 arctan(S / 2 d0) (Eq. 1,
+ * facing the target), the visual angle is lowered by mu per step and the
+ * distance at which it is reached is the next ring boundary, while the
+ * angle stays >= mu.  The last boundary is d_max, where V = mu (the
+ * distance beyond which no difference is perceivable; Sec. IV-B uses the
+ * same relation).  The k-th angle is computed as V0 - k mu.
+ *
+ * Bands of a ring: at the ring's middle distance d' the facing angle
+ * W_0 = 2 arctan(S / 2 d') is lowered by mu per step; each W_j is the visual
+ * angle of a perceived size S_j = 2 d' tan(W_j / 2), which Eq. 2 attributes
+ * to the viewing angle gamma_j = 90 deg * S_j / S.  The band boundaries are
+ * these angles, from 90 deg down, while W_j >= mu; the last band reaches 0. */
+int vo_partition(double S, double mu, double d0, vo_cells *out)
+{
+    memset(out, 0, sizeof(*out));
+    if (!(S > 0) || !(mu > 0) || !(d0 > 0))
+        return -1;
+    double V0 = 2.0 * atan(S / (2.0 * d0));
+    if (!(V0 > mu))
+        return -1;
+    int cap = 1024, nr = 0;
+    double *d = (double *)malloc(sizeof(double) * (size_t)cap);
+    d[0] = d0;
+    for (int k = 1;; ++k) {
+        double V = V0 - k * mu;
+        if (V < mu)
+            break;
+        if (k + 1 >= cap) {
+            cap *= 2;
+            d = (double *)realloc(d, sizeof(double) * (size_t)cap);
+        }
+        d[k] = S / (2.0 * tan(V / 2.0));
+        nr = k;
+    }
+    /* nr = K: boundaries d[0..K]; ring K ends at d_max */
+    if (nr + 2 >= cap)
+        d = (double *)realloc(d, sizeof(double) * (size_t)(nr + 2));
+    d[nr + 1] = S / (2.0 * tan(mu / 2.0));
+    int nring = nr + 1;
+    int64_t *boff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nring + 1));
+    int64_t gcap = 4096, gn = 0;
+    double *gam = (double *)malloc(sizeof(double) * (size_t)gcap);
+    for (int i = 0; i < nring; ++i) {
+        boff[i] = gn;
+        double dp = 0.5 * (d[i] + d[i + 1]);
+        double W0 = 2.0 * atan(S / (2.0 * dp));
+        if (gn + 2 >= gcap) {
+            gcap *= 2;
+            gam = (double *)realloc(gam, sizeof(double) * (size_t)gcap);
+        }
+        gam[gn++] = VO_PI / 2.0;
+        for (int j = 1;; ++j) {
+            double W = W0 - j * mu;
+            if (W < mu)
+                break;
+            double Sj = 2.0 * dp * tan(W / 2.0);
+            if (gn + 2 >= gcap) {
+                gcap *= 2;
+                gam = (double *)realloc(gam, sizeof(double) * (size_t)gcap);
+            }
+            gam[gn++] = (VO_PI / 2.0) * Sj / S;
+        }
+        gam[gn++] = 0.0;
+    }
+    boff[nring] = gn;
+    out->nring = nring;
+    out->d = d;
+    out->boff = boff;
+    out->gam = gam;
+    out->S = S;
+    out->mu = mu;
+    out->d0 = d0;
+    out->V0 = V0;
+    return 0;
+}
+
+void vo_free_cells(vo_cells *c)
+{
+    free(c->d);
+    free(c->boff);
+    free(c->gam);
+    memset(c, 0, sizeof(*c));
+}
+
+int vo_cells_size(const vo_cells *c, int64_t *n_bands_total) { *n_bands_total = c->boff[c->nring]; return c->nring; }
+void vo_cells_copy(const vo_cells *c, double *d, int64_t *boff, double *gam)
+{
+    memcpy(d, c->d, sizeof(double) * (size_t)(c->nring + 1));
+    memcpy(boff, c->boff, sizeof(int64_t) * (size_t)(c->nring + 1));
+    memcpy(gam, c->gam, sizeof(double) * (size_t)c->boff[c->nring]);
+}
+
+/* Visual angle at distance D and viewing angle alpha (Eq. 1 with Eq. 2). */
+static double vis_angle(double S, double D, double alpha)
+{
+    return 2.0 * atan((alpha / (VO_PI / 2.0)) * S / (2.0 * D));
+}
+
+/* Colour of cell (i, j): the visual angle at the cell's centre (Sec.
+ * III-A, after the partitioning steps), taken in parameter space as the
+ * ring's middle distance and the band's middle angle, divided by V0. */
+static double cell_colour(const vo_cells *c, int i, int j)
+{
+    const double *g = c->gam + c->boff[i];
+    double dp = 0.5 * (c->d[i] + c->d[i + 1]);
+    double gm = 0.5 * (g[j] + g[j + 1]);
+    return vis_angle(c->S, dp, gm) / c->V0;
+}
+
+static int n_bands(const vo_cells *c, int i) { return (int)(c->boff[i + 1] - c->boff[i]) - 1; }
+
+/* Band of viewing angle alpha in ring i: (gamma_{j+1}, gamma_j], the last
+ * band closed at 0. */
+static int band_of(const vo_cells *c, int i, double alpha)
+{
+    const double *g = c->gam + c->boff[i];
+    int L = n_bands(c, i);
+    for (int j = 0; j < L; ++j)
+        if (alpha > g[j + 1])
+            return j;
+    return L - 1;
+}
+
+/* Ring of distance D: [d_i, d_{i+1}); below d0 counts as ring 0; -1 at or
+ * beyond d_max. */
+static int ring_of(const vo_cells *c, double D)
+{
+    if (D >= c->d[c->nring])
+        return -1;
+    int i = 0;
+    while (i + 1 < c->nring && D >= c->d[i + 1])
+        ++i;
+    return i;
+}
+
+/* Per-viewpoint colours of the three pruned constructions from the
+ * meridian coordinates (D, alpha) of q (first quadrant, Sec. III-A-2):
+ *   E: colour of q's own cell;
+ *   M: colour of the first cell, lowest ring then lowest band, whose closed
+ *      MBR in the (rho, h) plane contains q (Sec. IV-A, MBR approximation);
+ *   T: colour of the first ring whose tangent trapezoid, the band of alpha
+ *      bounded by the tangents of the ring's arcs at the band's middle
+ *      angle, contains q (Sec. IV-A, tangential approximation); when no
+ *      trapezoid contains q the exact cell is used and *t_fallback set.
+ * Beyond d_max all three are 0.  out = {cE, cM, cT}; ring/band of E too. */
+void vo_pruned_colours(const vo_cells *c, double D, double alpha, double *out, int *cell,
+                       int *t_fallback)
+{
+    out[0] = out[1] = out[2] = 0.0;
+    cell[0] = cell[1] = -1;
+    *t_fallback = 0;
+    int ir = ring_of(c, D);
+    if (ir < 0)
+        return;
+    int jb = band_of(c, ir, alpha);
+    cell[0] = ir;
+    cell[1] = jb;
+    out[0] = cell_colour(c, ir, jb);
+    double rho = D * cos(alpha), h = D * sin(alpha);
+    /* MBR: the cell is the annular sector d in [d_i, d_{i+1}], angle in
+     * [gamma_{j+1}, gamma_j]; its bounding box in the (rho, h) quadrant. */
+    int found = 0;
+    for (int i = 0; i < c->nring && !found; ++i) {
+        /* a ring's MBRs lie within sqrt(2) d_{i+1} of the centre */
+        if (sqrt(2.0) * c->d[i + 1] < D)
+            continue;
+        const double *g = c->gam + c->boff[i];
+        int L = n_bands(c, i);
+        for (int j = 0; j < L; ++j) {
+            double r0 = c->d[i] * cos(g[j]), r1 = c->d[i + 1] * cos(g[j + 1]);
+            double h0 = c->d[i] * sin(g[j + 1]), h1 = c->d[i + 1] * sin(g[j]);
+            if (rho >= r0 && rho <= r1 && h >= h0 && h <= h1) {
+                out[1] = cell_colour(c, i, j);
+                found = 1;
+                break;
+            }
+        }
+    }
+    if (!found)
+        out[1] = out[0];
+    /* Tangents: for each ring, the band containing alpha and the projection
+     * of q on the direction of the band's middle angle. */
+    found = 0;
+    for (int i = 0; i < c->nring; ++i) {
+        int j = band_of(c, i, alpha);
+        const double *g = c->gam + c->boff[i];
+        double gm = 0.5 * (g[j] + g[j + 1]);
+        double p = D * cos(alpha - gm);
+        if (p >= c->d[i] && p < c->d[i + 1]) {
+            out[2] = cell_colour(c, i, j);
+            found = 1;
+            break;
+        }
+    }
+    if (!found) {
+        out[2] = out[0];
+        *t_fallback = 1;
+    }
+}
+
+/* Meridian coordinates of q relative to the target: D and alpha as in the
+ * measure (h along the normal axis, rho the rest). */
+static void meridian(const vo_target *t, const double *q, double *D, double *alpha)
+{
+    double dl[3];
+    for (int k = 0; k < 3; ++k)
+        dl[k] = q[k] - t->center[k];
+    if (t->kind == VO_SEGMENT)
+        dl[2] = 0.0;
+    int nax;
+    if (t->kind == VO_CUBE) {
+        nax = 0;
+        for (int k = 1; k < 3; ++k)
+            if (fabs(dl[k]) > fabs(dl[nax]))
+                nax = k;
+    } else {
+        nax = t->normal_axis;
+    }
+    double h = fabs(dl[nax]), r2 = 0.0;
+    for (int k = 0; k < 3; ++k)
+        if (k != nax)
+            r2 += dl[k] * dl[k];
+    *D = sqrt(r2 + h * h);
+    *alpha = atan2(h, sqrt(r2));
+}
+
+void vo_meridian(const vo_target *t, const double *q, double *out)
+{
+    meridian(t, q, &out[0], &out[1]);
+}
+
+/* Representative viewpoint of q for a minimum block size theta: the grid is
+ * cut into aligned blocks of theta viewpoints per axis and every viewpoint
+ * takes the visibility of its block's lowest-index centre viewpoint (Sec.
+ * III-C, blocks not split below theta; the baseline of Sec. V-B likewise
+ * uses one point per grid cell).  theta = 1 gives q itself. */
+int64_t vo_block_rep(const vo_grid *g, int dim, int theta, int64_t idx)
+{
+    int64_t ii[3] = {idx % g->n[0], (idx / g->n[0]) % g->n[1], idx / (g->n[0] * g->n[1])};
+    for (int a = 0; a < dim; ++a) {
+        int64_t b0 = (ii[a] / theta) * theta;
+        int64_t off = (theta - 1) / 2;
+        if (b0 + off > g->n[a] - 1)
+            off = g->n[a] - 1 - b0;
+        ii[a] = b0 + off;
+    }
+    return ii[0] + g->n[0] * (ii[1] + g->n[1] * ii[2]);
+}
+
+/* Pruned VCM at the listed viewpoints: method 1 = E, 2 = M, 3 = T.
+ * The gate (visible count and N(q), FOV) comes from the brute-force oracle
+ * at the block representative; the colour from the cell lookups at q.
+ * count/c/cb/bin as in vo_eval; cell_out: ring, band of q's own cell. */
+int vo_eval_pruned(int dim, int64_t nbox, const double *lo, const double *hi,
+                   const vo_target *t, const vo_grid *g, const vo_params *p,
+                   int method, int theta, const int64_t *vp, int64_t nvp, int nthreads,
+                   uint16_t *count, double *c, double *cb, uint8_t *bin, int32_t *cell_out,
+                   uint8_t *t_fallback)
+{
+    if (method < 1 || method > 3 || theta < 1)
+        return -1;
+    vo_cells cells;
+    double mu = p->mu_arcmin * VO_PI / (180.0 * 60.0);
+    if (vo_partition(target_size(t), mu, p->d0, &cells))
+        return -1;
+    int64_t *rep = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nvp > 0 ? nvp : 1));
+    for (int64_t v = 0; v < nvp; ++v)
+        rep[v] = vo_block_rep(g, dim, theta, vp[v]);
+    uint16_t *rc = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)(nvp > 0 ? nvp : 1));
+    uint16_t *rn = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)(nvp > 0 ? nvp : 1));
+    uint8_t *rf = (uint8_t *)malloc((size_t)(nvp > 0 ? nvp : 1));
+    int r = vo_eval(dim, nbox, lo, hi, t, g, p, rep, nvp, nthreads, rc, rn, rf, NULL, NULL, NULL);
+    if (r == 0) {
+        for (int64_t v = 0; v < nvp; ++v) {
+            int64_t idx = vp[v];
+            int64_t ii[3] = {idx % g->n[0], (idx / g->n[0]) % g->n[1], idx / (g->n[0] * g->n[1])};
+            double q[3] = {0.0, 0.0, 0.0};
+            for (int a = 0; a < dim; ++a)
+                q[a] = g->origin[a] + (double)(2 * ii[a] + 1) * (g->extent[a] / (2.0 * (double)g->n[a]));
+            double D, al, cols[3];
+            int cl[2], tf;
+            meridian(t, q, &D, &al);
+            vo_pruned_colours(&cells, D, al, cols, cl, &tf);
+            double craw = cols[method - 1];
+            int n = rn[v], vis = rc[v];
+            double col;
+            int cnt = vis;
+            if (!rf[v] || n == 0)
+                col = 0.0;
+            else if (p->mode == VO_FRACTION)
+                col = ((double)vis / (double)n) * craw;
+            else
+                col = (vis == n) ? craw : 0.0;
+            double cbv;
+            uint8_t bn;
+            to_bin(p, col, cells.V0, &cbv, &bn);
+            if (count) count[v] = (uint16_t)cnt;
+            if (c) c[v] = col;
+            if (cb) cb[v] = cbv;
+            if (bin) bin[v] = bn;
+            if (cell_out) {
+                cell_out[2 * v] = cl[0];
+                cell_out[2 * v + 1] = cl[1];
+            }
+            if (t_fallback) t_fallback[v] = (uint8_t)tf;
+        }
+    }
+    free(rep);
+    free(rc);
+    free(rn);
+    free(rf);
+    vo_free_cells(&cells);
+    return r;
+}
+
+/* Approximation error of Sec. V-A: sum_i (c_e A - c_a A) / sum_i c_e A over
+ * equal-size viewpoint cells, and the same with |c_e - c_a|. */
+void vo_map_error(const double *ce, const double *ca, int64_t n, double *signed_err, double *abs_err)
+{
+    double num = 0.0, den = 0.0, ab = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        num += ce[i] - ca[i];
+        ab += fabs(ce[i] - ca[i]);
+        den += ce[i];
+    }
+    *signed_err = den > 0 ? num / den : 0.0;
+    *abs_err = den > 0 ? ab / den : 0.0;
+}
+
+/* Error bounds of Sec. IV-A, evaluated as printed, per ring i with radii
+ * r_i = d_i, r_{i+1} = d_{i+1}:
+ *   MBR:     dr = sqrt(2) r_{i+1};             bands counted below
+ *            arctan(r_{i+1} / (S/2));
+ *   tangent: dr = sqrt(r_{i+1}^2 + (r_{i+1} - r_i)^2); bands counted below
+ *            arctan(r_{i+1} / (S/2 + r_i));
+ *   n = (dr - r_{i+1}) / (r_{i+1} - r_i), a_i = number of such bands,
+ *   dc = n a_i mu, E = sum over the ring's cells of dc * A_cell,
+ * A_cell the cell's area in the (rho, h) quadrant (2-D) or its volume of
+ * revolution about the normal axis (3-D).  out = {E_MBR, E_Tangent}. */
+void vo_error_bounds(const vo_cells *c, int dim, double *out)
+{
+    double E[2] = {0.0, 0.0};
+    for (int i = 0; i < c->nring; ++i) {
+        double r0 = c->d[i], r1 = c->d[i + 1];
+        if (!(r1 > r0))
+            continue;
+        const double *g = c->gam + c->boff[i];
+        int L = n_bands(c, i);
+        double drs[2] = {sqrt(2.0) * r1, sqrt(r1 * r1 + (r1 - r0) * (r1 - r0))};
+        double lim[2] = {atan(r1 / (c->S / 2.0)), atan(r1 / (c->S / 2.0 + r0))};
+        for (int m = 0; m < 2; ++m) {
+            double n = (drs[m] - r1) / (r1 - r0);
+            int a = 0;
+            for (int j = 0; j < L; ++j)
+                if (g[j + 1] < lim[m])
+                    ++a;
+            double dc = n * a * c->mu;
+            double area = 0.0;
+            for (int j = 0; j < L; ++j) {
+                double g0 = g[j + 1], g1 = g[j];
+                if (dim == 2)
+                    area += 0.5 * (g1 - g0) * (r1 * r1 - r0 * r0);
+                else /* revolve the sector about the h axis: 2 pi * int rho dA */
+                    area += 2.0 * VO_PI * (r1 * r1 * r1 - r0 * r0 * r0) / 3.0 * (sin(g1) - sin(g0));
+            }
+            E[m] += dc * area;
+        }
+    }
+    out[0] = E[0];
+    out[1] = E[1];
+}
