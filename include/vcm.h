@@ -179,6 +179,8 @@ typedef struct {
     uint64_t columns;        /* grid columns visited                         */
     uint64_t slot_tests;     /* wavefront-level slab tests (64 lanes each)   */
     uint64_t inside_box;     /* viewpoints found inside an obstacle          */
+    uint64_t t_fallbacks;    /* VCM_PRUNED_T: viewpoints no tangent trapezoid
+                                contained (coloured by their exact cell)    */
     double kernel_ms;        /* device time of the call's kernels            */
 } vcm_stats;
 

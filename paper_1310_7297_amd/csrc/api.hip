@@ -127,9 +127,10 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
     if (P.bin_scale != VCM_BIN_LINEAR && P.bin_scale != VCM_BIN_LOG)
         return set_error(VCM_E_INVALID, "unknown bin_scale");
     if (P.mode != VCM_FULL && P.mode != VCM_FRACTION) return set_error(VCM_E_INVALID, "unknown mode");
-    if (P.method != VCM_BRUTE)
-        return set_error(VCM_E_INVALID, "method not available in vcm_compute of this build");
-    if (P.theta_blocks < 1) return set_error(VCM_E_INVALID, "theta_blocks must be >= 1");
+    if (P.method < VCM_BRUTE || P.method > VCM_PRUNED_T)
+        return set_error(VCM_E_INVALID, "unknown method");
+    if (P.theta_blocks < 1 || P.theta_blocks > 4096)
+        return set_error(VCM_E_INVALID, "theta_blocks must be in [1, 4096]");
     if (!(P.recheck_eps >= 0)) return set_error(VCM_E_INVALID, "recheck_eps must be >= 0");
     if (P.precision != VCM_FP32_RECHECK && P.precision != VCM_FP64)
         return set_error(VCM_E_INVALID, "unknown precision");
@@ -187,12 +188,35 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
     p->V0 = (float)V0;
     p->inv_V0 = (float)(1.0 / V0);
     p->mu = (float)mu;
+    p->mu_d = mu;
+    p->d0_d = P.near_d0;
     p->inv_log_V0_mu = (float)(1.0 / std::log(V0 / mu));
     p->eps = (float)P.recheck_eps;  // +inf stays +inf: every test goes to the exact predicate
     p->eps_ref = 0x1p-20f;
     p->fp64 = P.precision == VCM_FP64 ? 1 : 0;
 
     return VCM_OK;
+}
+
+vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
+                     int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats) {
+    if (method == VCM_BRUTE) return launch_brute(ix, t, g, p, r, s, stats);
+    // pruned: gate at the block representatives, then the cell colours
+    int32_t gn[3];
+    int64_t nrep = 1;
+    for (int k = 0; k < 3; ++k) {
+        gn[k] = (g.n[k] + theta - 1) / theta;
+        nrep *= gn[k];
+    }
+    uint32_t *gate = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&gate), sizeof(uint32_t) * nrep, s);
+    if (e != hipSuccess) return set_error(VCM_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    vcm_status st = launch_brute(ix, t, g, p, r, s, stats, gate, theta);
+    if (st == VCM_OK)
+        st = launch_pruned(ix, t, g, p, method, theta, gate, gn, r, s,
+                           stats ? &stats->t_fallbacks : nullptr);
+    hipFreeAsync(gate, s);
+    return st;
 }
 
 }  // namespace vcm
@@ -291,16 +315,19 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     if (st != VCM_OK) return st;
     DeviceGuard guard(ix.device);
     hipStream_t s = (hipStream_t)stream;
-    if (!stats) return launch_brute(ix, t, g, p, *result, s, nullptr);
 
     DevStats *d_stats = nullptr;
-    TRY_HIP(hipMalloc(&d_stats, sizeof(DevStats)));
-    hipEvent_t e0, e1;
-    TRY_HIP(hipEventCreate(&e0));
-    TRY_HIP(hipEventCreate(&e1));
-    TRY_HIP(hipMemsetAsync(d_stats, 0, sizeof(DevStats), s));
-    TRY_HIP(hipEventRecord(e0, s));
-    st = launch_brute(ix, t, g, p, *result, s, d_stats);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        TRY_HIP(hipMalloc(&d_stats, sizeof(DevStats)));
+        TRY_HIP(hipEventCreate(&e0));
+        TRY_HIP(hipEventCreate(&e1));
+        TRY_HIP(hipMemsetAsync(d_stats, 0, sizeof(DevStats), s));
+        TRY_HIP(hipEventRecord(e0, s));
+    }
+    st = run_query(ix, t, g, p, query->params.method, query->params.theta_blocks, *result, s,
+                   d_stats);
+    if (!stats) return st;
     TRY_HIP(hipEventRecord(e1, s));
     DevStats h{};
     TRY_HIP(hipMemcpyAsync(&h, d_stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
@@ -319,6 +346,7 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     stats->columns = h.columns;
     stats->slot_tests = h.slot_tests;
     stats->inside_box = h.inside_box;
+    stats->t_fallbacks = h.t_fallbacks;
     stats->kernel_ms = ms;
     return VCM_OK;
 }

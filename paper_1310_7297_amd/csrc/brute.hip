@@ -482,8 +482,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         uint8_t o_bin = 0;
         float o_c = 0.0f;
         uint16_t o_cnt = 0;
+        uint32_t o_gate = 0;
         for (int t = 0; t < nv; ++t) {
-            const int ii[3] = {x0 + t, jj, kk};
+            // grid index; in gate mode the launch grid is the block grid and
+            // each block is represented by its lowest-index centre viewpoint
+            int ii[3] = {x0 + t, jj, kk};
+            if (A.gate) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    ii[k] = min(ii[k] * A.theta + (A.theta - 1) / 2, A.full_n[k] - 1);
+            }
             float q[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
@@ -532,12 +540,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                 o_bin = static_cast<uint8_t>(bn);
                 o_c = static_cast<float>(col);
                 o_cnt = static_cast<uint16_t>(cnt);
+                o_gate = static_cast<uint32_t>(cnt) | (static_cast<uint32_t>(N) << 10) |
+                         (fov ? (1u << 20) : 0u);
             }
         }
         if (lane < nv) {
-            A.bin[v0 + lane] = o_bin;
-            if (A.c) A.c[v0 + lane] = o_c;
-            if (A.count) A.count[v0 + lane] = o_cnt;
+            if (A.gate) {
+                A.gate[v0 + lane] = o_gate;
+            } else {
+                A.bin[v0 + lane] = o_bin;
+                if (A.c) A.c[v0 + lane] = o_c;
+                if (A.count) A.count[v0 + lane] = o_cnt;
+            }
         }
     }
     if (STATS) {
@@ -607,11 +621,23 @@ int device_cus(int device) {
 
 }  // namespace
 
-vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g,
+vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_in,
                         const ParamDesc &p, const vcm_result &r, hipStream_t stream,
-                        DevStats *stats) {
-    if (g.count <= 0) return VCM_OK;
+                        DevStats *stats, uint32_t *gate, int theta) {
+    if (g_in.count <= 0) return VCM_OK;
     BruteArgs a{};
+    GridDesc g = g_in;
+    a.theta = theta;
+    for (int k = 0; k < 3; ++k) a.full_n[k] = g_in.n[k];
+    if (gate) {
+        // launch over the block grid
+        g.count = 1;
+        for (int k = 0; k < 3; ++k) {
+            g.n[k] = (g_in.n[k] + theta - 1) / theta;
+            g.count *= g.n[k];
+        }
+    }
+    a.gate = gate;
     a.idx = ix.dev;
     a.tgt = t;
     a.grid = g;

@@ -1,0 +1,286 @@
+// Pruned VCM construction: equi-visible cells (Sec. III-A) joined with the
+// visibility gate, exactly (VCM_E) or through the MBR and tangential cell
+// approximations of Sec. IV-A (VCM_M, VCM_T).
+//
+// The paper builds a colour tree of cells and joins it with a quad-tree of
+// visible regions.  On the GPU every viewpoint instead finds its cell in
+// closed form: ring i satisfies V(d_i) = V0 - i mu at the facing angle, so
+// i = floor((V0 - V(D)) / mu) up to rounding, and the band likewise from the
+// visual angle at the ring's middle distance.  Each guess is then settled by
+// comparing against the boundary values themselves, which are evaluated in
+// float64 with the same expressions that define them.  One thread per
+// viewpoint; the gate (visible count, live samples, field of view) comes
+// from the ray-casting kernel run at the block representatives.
+#include <cmath>
+
+#include "vcm_internal.h"
+
+namespace vcm {
+namespace {
+
+struct CellFrame {
+    double S, mu, d0, V0, dmax;
+    int K;  // rings 0..K; ring K ends at dmax
+};
+
+// Boundary radius d_i (d_0 = near point, d_{K+1} = d_max).
+__device__ inline double ring_d(const CellFrame &F, int i) {
+    if (i <= 0) return F.d0;
+    if (i > F.K) return F.dmax;
+    const double V = F.V0 - i * F.mu;
+    return F.S / (2.0 * tan(V / 2.0));
+}
+
+__device__ inline double vis_angle(double S, double D, double alpha) {
+    return 2.0 * atan((alpha / (M_PI / 2.0)) * S / (2.0 * D));
+}
+
+// Ring of distance D, or -1 at or beyond d_max.
+__device__ inline int ring_of(const CellFrame &F, double D) {
+    if (D >= F.dmax) return -1;
+    const double Dn = D > F.d0 ? D : F.d0;
+    const double V90 = 2.0 * atan(F.S / (2.0 * Dn));
+    int i = static_cast<int>(floor((F.V0 - V90) / F.mu));
+    i = max(0, min(F.K, i));
+    while (i > 0 && D < ring_d(F, i)) --i;
+    while (i < F.K && D >= ring_d(F, i + 1)) ++i;
+    return i;
+}
+
+// Bands of one ring: gamma_0 = pi/2 > gamma_1 > ... > gamma_L > gamma_{L+1} = 0.
+struct Ring {
+    double dl, dh, dp, W0;
+    int L;
+};
+
+__device__ inline Ring make_ring(const CellFrame &F, int i) {
+    Ring r;
+    r.dl = ring_d(F, i);
+    r.dh = ring_d(F, i + 1);
+    r.dp = 0.5 * (r.dl + r.dh);
+    r.W0 = 2.0 * atan(F.S / (2.0 * r.dp));
+    int L = max(0, static_cast<int>(floor((r.W0 - F.mu) / F.mu)));
+    while (r.W0 - (L + 1) * F.mu >= F.mu) ++L;
+    while (L > 0 && r.W0 - L * F.mu < F.mu) --L;
+    r.L = L;
+    return r;
+}
+
+__device__ inline double gamma_of(const CellFrame &F, const Ring &r, int j) {
+    if (j <= 0) return M_PI / 2.0;
+    if (j > r.L) return 0.0;
+    const double W = r.W0 - j * F.mu;
+    const double Sj = 2.0 * r.dp * tan(W / 2.0);
+    return (M_PI / 2.0) * Sj / F.S;
+}
+
+// Band of viewing angle alpha: (gamma_{j+1}, gamma_j]; the last one closed at 0.
+__device__ inline int band_of(const CellFrame &F, const Ring &r, double alpha) {
+    const double V = vis_angle(F.S, r.dp, alpha);
+    int j = static_cast<int>(floor((r.W0 - V) / F.mu));
+    j = max(0, min(r.L, j));
+    while (j > 0 && alpha > gamma_of(F, r, j)) --j;
+    while (j < r.L && alpha <= gamma_of(F, r, j + 1)) ++j;
+    return j;
+}
+
+__device__ inline double cell_colour(const CellFrame &F, const Ring &r, int j) {
+    const double gm = 0.5 * (gamma_of(F, r, j) + gamma_of(F, r, j + 1));
+    return vis_angle(F.S, r.dp, gm) / F.V0;
+}
+
+// Smallest j in [0, L] with pred(j) true for a predicate that is false then
+// true as j grows; L + 1 if none.  Starts from a guess.
+template <typename P>
+__device__ inline int first_true(int guess, int L, P pred) {
+    int j = max(0, min(L + 1, guess));
+    while (j > 0 && pred(j - 1)) --j;
+    while (j <= L && !pred(j)) ++j;
+    return j;
+}
+
+// Band index whose boundary gamma_k first drops to <= theta (k in 0..L+1).
+__device__ inline int first_gamma_below(const CellFrame &F, const Ring &r, double theta) {
+    const double V = vis_angle(F.S, r.dp, fmax(theta, 0.0));
+    const int guess = static_cast<int>(ceil((r.W0 - V) / F.mu));
+    int k = max(0, min(r.L + 1, guess));
+    while (k > 0 && gamma_of(F, r, k - 1) <= theta) --k;
+    while (k <= r.L && gamma_of(F, r, k) > theta) ++k;
+    return k;
+}
+
+struct PrunedArgs {
+    CellFrame F;
+    TargetDesc tgt;
+    GridDesc grid;
+    ParamDesc prm;
+    const uint32_t *gate;  // per representative: count | N << 10 | fov << 20
+    int32_t theta;
+    int32_t method;        // VCM_PRUNED_E / M / T
+    int32_t gn[3];         // representative grid
+    int32_t dim;
+    uint8_t *bin;
+    float *c;
+    uint16_t *count;
+    unsigned long long *fallback;  // tangent lookups that fell back (optional)
+};
+
+__global__ __launch_bounds__(256) void k_pruned(PrunedArgs A) {
+    const int64_t vp = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (vp >= A.grid.count) return;
+    const int n0 = A.grid.n[0], n1 = A.grid.n[1];
+    const int ii[3] = {static_cast<int>(vp % n0), static_cast<int>((vp / n0) % n1),
+                       static_cast<int>(vp / (static_cast<int64_t>(n0) * n1))};
+    // viewpoint, relative to the target centre (exact)
+    double dl[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < A.dim; ++k)
+        dl[k] = (double(A.grid.o[k]) + double(2 * ii[k] + 1) * double(A.grid.h2[k])) -
+                double(A.tgt.c[k]);
+    int nax = A.tgt.nax;
+    if (A.tgt.kind == VCM_CUBE) {
+        nax = 0;
+        if (fabs(dl[1]) > fabs(dl[nax])) nax = 1;
+        if (fabs(dl[2]) > fabs(dl[nax])) nax = 2;
+    }
+    const double h = fabs(dl[nax]);
+    double r2 = 0.0;
+    for (int k = 0; k < 3; ++k)
+        if (k != nax) r2 += dl[k] * dl[k];
+    const double D = sqrt(r2 + h * h);
+    const double alpha = atan2(h, sqrt(r2));
+    const double rho = D * cos(alpha), hh = D * sin(alpha);
+
+    // gate of the block representative
+    int64_t rep = 0;
+    {
+        int b[3];
+        for (int k = 0; k < 3; ++k) b[k] = (k < A.dim) ? ii[k] / A.theta : 0;
+        rep = b[0] + static_cast<int64_t>(A.gn[0]) * (b[1] + static_cast<int64_t>(A.gn[1]) * b[2]);
+    }
+    const uint32_t gw = A.gate[rep];
+    const int vis = static_cast<int>(gw & 1023u), N = static_cast<int>((gw >> 10) & 1023u);
+    const bool fov = (gw >> 20) & 1u;
+
+    const CellFrame &F = A.F;
+    double craw = 0.0;
+    bool fell_back = false;
+    const int iq = ring_of(F, D);
+    if (iq >= 0 && fov && N > 0 && vis > 0) {
+        const Ring rq = make_ring(F, iq);
+        const int jq = band_of(F, rq, alpha);
+        const double ce = cell_colour(F, rq, jq);
+        craw = ce;
+        if (A.method == VCM_PRUNED_M) {
+            // lowest ring, then lowest band, whose closed MBR contains (rho, h);
+            // a ring's MBRs lie within sqrt(2) d_{i+1} of the centre
+            int i0 = ring_of(F, D / sqrt(2.0));
+            i0 = i0 < 0 ? 0 : i0;
+            while (i0 > 0 && sqrt(2.0) * ring_d(F, i0) >= D) --i0;
+            bool found = false;
+            for (int i = i0; i <= iq && !found; ++i) {
+                if (sqrt(2.0) * ring_d(F, i + 1) < D) continue;
+                const Ring r = make_ring(F, i);
+                // rho <= d_{i+1} cos(gamma_{j+1})  <=>  gamma_{j+1} <= acos(rho / d_{i+1})
+                int jB = rho <= r.dh ? first_gamma_below(F, r, acos(rho / r.dh)) - 1 : r.L + 1;
+                // d_i sin(gamma_{j+1}) <= h  <=>  gamma_{j+1} <= asin(h / d_i)
+                int jC = hh >= r.dl ? 0 : first_gamma_below(F, r, asin(hh / r.dl)) - 1;
+                jB = max(jB, 0);
+                jC = max(jC, 0);
+                const int j = max(jB, jC);
+                if (j > r.L) continue;
+                const double g0 = gamma_of(F, r, j), g1 = gamma_of(F, r, j + 1);
+                const bool in = rho >= r.dl * cos(g0) && rho <= r.dh * cos(g1) &&
+                                hh >= r.dl * sin(g1) && hh <= r.dh * sin(g0);
+                if (in) {
+                    craw = cell_colour(F, r, j);
+                    found = true;
+                }
+            }
+        } else if (A.method == VCM_PRUNED_T) {
+            // lowest ring whose tangent trapezoid (band of alpha, projection on
+            // the band's middle direction in [d_i, d_{i+1})) contains q; the
+            // projection is at least D cos(45 deg)
+            int i0 = ring_of(F, D * sqrt(0.5));
+            i0 = i0 < 0 ? 0 : i0;
+            while (i0 > 0 && ring_d(F, i0) > D * sqrt(0.5)) --i0;
+            bool found = false;
+            for (int i = i0; i <= iq && !found; ++i) {
+                const Ring r = make_ring(F, i);
+                const int j = band_of(F, r, alpha);
+                const double gm = 0.5 * (gamma_of(F, r, j) + gamma_of(F, r, j + 1));
+                const double p = D * cos(alpha - gm);
+                if (p >= r.dl && p < r.dh) {
+                    craw = cell_colour(F, r, j);
+                    found = true;
+                }
+            }
+            fell_back = !found;
+        }
+    }
+    double col = 0.0;
+    int cnt = vis;
+    if (fov && N > 0) {
+        if (A.prm.mode == VCM_FRACTION)
+            col = (double(vis) / double(N)) * craw;
+        else
+            col = vis == N ? craw : 0.0;
+    }
+    double cb = col;
+    if (A.prm.bin_scale == VCM_BIN_LOG) {
+        const double veff = col * F.V0;
+        const double mu = F.mu;
+        cb = veff <= mu ? 0.0 : fmin(1.0, log(veff / mu) / log(F.V0 / mu));
+    }
+    const int bn = min(A.prm.n_bins - 1, static_cast<int>(floor(cb * A.prm.n_bins)));
+    A.bin[vp] = static_cast<uint8_t>(bn);
+    if (A.c) A.c[vp] = static_cast<float>(col);
+    if (A.count) A.count[vp] = static_cast<uint16_t>(cnt);
+    if (A.fallback && fell_back) atomicAdd(A.fallback, 1ull);
+}
+
+}  // namespace
+
+int count_rings(double S, double mu, double d0, double *V0) {
+    *V0 = 2.0 * std::atan(S / (2.0 * d0));
+    int K = 0;
+    for (int k = 1;; ++k) {
+        if (*V0 - k * mu < mu) break;
+        K = k;
+    }
+    return K;
+}
+
+vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g,
+                         const ParamDesc &p, int method, int theta, const uint32_t *gate,
+                         const int32_t gn[3], const vcm_result &r, hipStream_t stream,
+                         unsigned long long *fallback) {
+    PrunedArgs a{};
+    double V0;
+    const double mu = p.mu_d;
+    a.F.S = t.S;
+    a.F.mu = mu;
+    a.F.d0 = p.d0_d;
+    a.F.K = count_rings(t.S, mu, p.d0_d, &V0);
+    a.F.V0 = V0;
+    a.F.dmax = t.S / (2.0 * std::tan(mu / 2.0));
+    a.tgt = t;
+    a.grid = g;
+    a.prm = p;
+    a.gate = gate;
+    a.theta = theta;
+    a.method = method;
+    for (int k = 0; k < 3; ++k) a.gn[k] = gn[k];
+    a.dim = ix.dim;
+    a.bin = r.bin;
+    a.c = r.c;
+    a.count = r.count;
+    a.fallback = fallback;
+    const int64_t nblk = (g.count + 255) / 256;
+    hipLaunchKernelGGL(k_pruned, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(VCM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return VCM_OK;
+}
+
+}  // namespace vcm

@@ -82,6 +82,8 @@ struct ParamDesc {
     float inv_log_V0_mu;
     float eps;          // slab-test margin (+inf: every test exact)
     float eps_ref;      // the default margin (disagreement statistics)
+    double mu_d;        // angular resolution and near point in float64
+    double d0_d;
     int32_t fp64;       // every ray test exact in float64, measure in float64
 };
 
@@ -94,7 +96,7 @@ struct DevStats {
     unsigned long long columns;
     unsigned long long slot_tests;
     unsigned long long inside_box;
-    unsigned long long pad;
+    unsigned long long t_fallbacks;
 };
 
 // Everything one brute-force launch needs (passed by value).
@@ -108,6 +110,9 @@ struct BruteArgs {
     uint16_t *count;
     DevStats *stats;
     unsigned *counter;  // work-item counter (zeroed before the launch)
+    uint32_t *gate;     // gate mode: per block, count | N << 10 | fov << 20
+    int32_t theta;      // block size in viewpoints (gate mode)
+    int32_t full_n[3];  // the viewpoint grid (gate mode)
     int32_t k_begin;    // first z layer of this launch
     uint32_t n_items;   // work items in this launch
 };
@@ -139,7 +144,18 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
 // Launch the brute-force kernel over [vp_begin, vp_end) on `stream`.
 vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g,
                         const ParamDesc &p, const vcm_result &r, hipStream_t stream,
-                        DevStats *stats);
+                        DevStats *stats, uint32_t *gate = nullptr, int theta = 1);
+
+// Pruned colouring (E / M / T) of every viewpoint from the block gates.
+vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g,
+                         const ParamDesc &p, int method, int theta, const uint32_t *gate,
+                         const int32_t gn[3], const vcm_result &r, hipStream_t stream,
+                         unsigned long long *fallback);
+int count_rings(double S, double mu, double d0, double *V0);
+
+// One query on one stream: brute force, or gates plus pruned colouring.
+vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
+                     int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats);
 
 // Build the column index on the device.
 vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, int64_t n,
