@@ -203,6 +203,23 @@ typedef struct {
 vcm_status vcm_compute(const vcm_index *index, const vcm_query *query,
                        const vcm_result *result, void *stream, vcm_stats *stats);
 
+/* Approximation error of Sec. V-A between two colour maps of n viewpoints
+ * (caller-owned device buffers, one float each), every viewpoint standing
+ * for the same area:  out[0] = sum(c_exact - c_approx) / sum(c_exact)
+ * (signed), out[1] = sum|c_exact - c_approx| / sum(c_exact).  Both are 0
+ * when sum(c_exact) is 0.  Waits for `stream`. */
+vcm_status vcm_map_error(const float *c_exact, const float *c_approx, int64_t n, int32_t device,
+                         void *stream, double out[2]);
+
+/* Error bounds of the MBR (out[0]) and tangential (out[1]) approximations
+ * (Sec. IV-A, the sums E_MBR and E_Tangent) for the query's target size, mu
+ * and near point, evaluated as printed: per ring, the number of rings that
+ * can be mis-coloured times the number of bands below the stated angle times
+ * mu, weighted by the size of each cell of the ring (area in the meridian
+ * quadrant for dim 2, volume of revolution about the normal for dim 3).
+ * Host computation. */
+vcm_status vcm_error_bounds(const vcm_query *query, int32_t dim, double out[2]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,7 @@ VCM_FP32_RECHECK, VCM_FP64 = 0, 1
 
 # Every symbol include/vcm.h declares.
 EXPORTS = ("vcm_last_error", "vcm_version", "vcm_build_index", "vcm_free_index",
-           "vcm_index_get_info", "vcm_compute")
+           "vcm_index_get_info", "vcm_compute", "vcm_map_error", "vcm_error_bounds")
 
 
 class VcmError(RuntimeError):
@@ -117,7 +117,12 @@ def load_library(path: Optional[str] = None):
     L.vcm_compute.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_query),
                               ctypes.POINTER(vcm_result), ctypes.c_void_p,
                               ctypes.POINTER(vcm_stats)]
-    for name in ("vcm_build_index", "vcm_free_index", "vcm_index_get_info", "vcm_compute"):
+    L.vcm_map_error.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_double * 2)]
+    L.vcm_error_bounds.argtypes = [ctypes.POINTER(vcm_query), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_double * 2)]
+    for name in ("vcm_build_index", "vcm_free_index", "vcm_index_get_info", "vcm_compute",
+                 "vcm_map_error", "vcm_error_bounds"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -248,6 +253,25 @@ def vcm_compute(index: Index, query: scenes.Query, bin_out, c_out=None, count_ou
     if stats:
         return {f: getattr(st, f) for f, _ in vcm_stats._fields_}
     return None
+
+
+def vcm_map_error(c_exact, c_approx, stream=None):
+    """Signed and absolute approximation error (Sec. V-A) of two device maps."""
+    out = (ctypes.c_double * 2)()
+    n = c_exact.numel()
+    if c_approx.numel() != n:
+        raise ValueError("maps differ in size")
+    _check(load_library().vcm_map_error(c_exact.data_ptr(), c_approx.data_ptr(), n,
+                                        c_exact.device.index or 0, _stream_ptr(stream),
+                                        ctypes.byref(out)))
+    return out[0], out[1]
+
+
+def vcm_error_bounds(query: scenes.Query, dim: int):
+    out = (ctypes.c_double * 2)()
+    Q = make_query(query)
+    _check(load_library().vcm_error_bounds(ctypes.byref(Q), int(dim), ctypes.byref(out)))
+    return {"mbr": out[0], "tangent": out[1]}
 
 
 def alloc_result(n: int, device="cuda"):

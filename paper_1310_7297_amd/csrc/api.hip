@@ -351,4 +351,26 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     return VCM_OK;
 }
 
+vcm_status vcm_map_error(const float *c_exact, const float *c_approx, int64_t n, int device,
+                         void *stream, double out[2]) {
+    clear_error();
+    if (!out || n < 0 || (n > 0 && (!c_exact || !c_approx)))
+        return set_error(VCM_E_INVALID, "invalid arguments");
+    DeviceGuard guard(device);
+    return map_error(c_exact, c_approx, n, (hipStream_t)stream, out);
+}
+
+vcm_status vcm_error_bounds(const vcm_query *query, int32_t dim, double out[2]) {
+    clear_error();
+    if (!query || !out || (dim != 2 && dim != 3)) return set_error(VCM_E_INVALID, "invalid arguments");
+    const vcm_target &T = query->target;
+    const double S = T.kind == VCM_BILLBOARD ? std::max(T.size[0], T.size[1]) : T.size[0];
+    const double mu = query->params.mu_arcmin / 60.0 * M_PI / 180.0;
+    const double d0 = query->params.near_d0;
+    if (!(S > 0) || !(mu > 0) || !(d0 > 0) || !(2.0 * std::atan(S / (2.0 * d0)) > mu))
+        return set_error(VCM_E_INVALID, "target size, mu and near point must be positive, V0 > mu");
+    error_bounds(S, mu, d0, dim, out);
+    return VCM_OK;
+}
+
 }  // extern "C"

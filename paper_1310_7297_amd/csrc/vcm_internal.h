@@ -153,6 +153,9 @@ vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g
                          unsigned long long *fallback);
 int count_rings(double S, double mu, double d0, double *V0);
 
+vcm_status map_error(const float *ce, const float *ca, int64_t n, hipStream_t s, double *out);
+void error_bounds(double S, double mu, double d0, int dim, double *out);
+
 // One query on one stream: brute force, or gates plus pruned colouring.
 vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
                      int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats);

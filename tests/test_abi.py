@@ -64,3 +64,21 @@ def test_every_kernel_stub_has_device_code():
     syms = set(m.decode() for m in _re.findall(rb"(_Z\w+)\.kd", data))
     for s in names:
         assert any(s in k for k in syms), s
+
+
+@pytest.mark.parametrize("cfg,dim", [("config1", 2), ("config2", 3), ("config3", 3)])
+def test_error_bounds_match_oracle(cfg, dim):
+    """vcm_error_bounds is a host computation; it equals the oracle's sums."""
+    import math
+    import oracle
+    from paper_1310_7297_amd import scenes
+    _, q = getattr(scenes, cfg)()
+    t = q.target
+    S = max(t.size[0], t.size[1]) if t.kind == scenes.BILLBOARD else t.size[0]
+    cells = oracle.Cells(S, q.params.mu_arcmin / 60 * math.pi / 180, q.params.near_d0)
+    want = cells.error_bounds(dim)
+    got = vcm.vcm_error_bounds(q, dim)
+    assert got["mbr"] == pytest.approx(want["mbr"], rel=1e-12)
+    assert got["tangent"] == pytest.approx(want["tangent"], rel=1e-12)
+    with pytest.raises(vcm.VcmError):
+        vcm.vcm_error_bounds(q, 4)

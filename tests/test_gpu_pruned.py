@@ -139,3 +139,39 @@ def test_pruned_gate_matches_brute_map():
     for m in (1, 2, 3):
         p = _gpu_map(scene, _with(q, method=m))
         assert np.array_equal(p["count"], b["count"])
+
+
+def test_map_error_matches_oracle():
+    """Sec. V-A error of the M and T maps against the E map, reduced on the
+    device, equals the oracle's float64 sums over the same colours."""
+    import torch
+    scene, q = scenes.config1()
+    maps = {m: _gpu_map(scene, _with(q, method=m, mode=FULL)) for m in (1, 2, 3)}
+    for m in (2, 3):
+        ce = torch.from_numpy(maps[1]["c"]).cuda()
+        ca = torch.from_numpy(maps[m]["c"]).cuda()
+        got = vcm.vcm_map_error(ce, ca)
+        want = oracle.map_error(maps[1]["c"], maps[m]["c"])
+        assert got == pytest.approx(want, rel=1e-12, abs=1e-15)
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 255, 257, 1 << 20, (1 << 20) + 77])
+def test_map_error_sizes(n):
+    import torch
+    rng = np.random.default_rng(n)
+    ce = rng.random(n).astype(np.float32)
+    ca = (ce * rng.uniform(0.5, 1.5, n)).astype(np.float32)
+    got = vcm.vcm_map_error(torch.from_numpy(ce).cuda(), torch.from_numpy(ca).cuda())
+    want = oracle.map_error(ce, ca)
+    assert got == pytest.approx(want, rel=1e-11, abs=1e-15)
+
+
+def test_map_error_worked_case():
+    import torch
+    ce = torch.tensor([1.0, 0.5, 0.0, 0.25], device="cuda")
+    ca = torch.tensor([0.5, 0.5, 0.25, 0.5], device="cuda")
+    s, a = vcm.vcm_map_error(ce, ca)
+    assert s == pytest.approx((0.5 - 0.25 - 0.25) / 1.75, abs=1e-15)
+    assert a == pytest.approx((0.5 + 0.25 + 0.25) / 1.75, rel=1e-15)
+    z = torch.zeros(5, device="cuda")
+    assert vcm.vcm_map_error(z, ce.new_ones(5)) == (0.0, 0.0)
