@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--config", type=int, default=3, choices=(2, 3))
     ap.add_argument("--mode", default="fraction", choices=("fraction", "full"))
     ap.add_argument("--cell", type=float, default=0.0)
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

@@ -34,6 +34,10 @@
  *     the colour by the visible fraction of live samples (an extension).
  *   - Linear colour bins: bin = min(B-1, floor(c B)); the log scale is a test
  *     aid that spreads visual angles between mu and V0 over the bins.
+ *
+ * Every function is pinned by tests against closed forms, invariants, brute
+ * force on tiny inputs or the paper's worked example, except the error
+ * bounds of Sec. IV-A (vo_error_bounds): parity unpinned beyond their order.
  */
 #include <math.h>
 #include <pthread.h>
@@ -842,7 +846,9 @@ void vo_map_error(const double *ce, const double *ca, int64_t n, double *signed_
  *   n = (dr - r_{i+1}) / (r_{i+1} - r_i), a_i = number of such bands,
  *   dc = n a_i mu, E = sum over the ring's cells of dc * A_cell,
  * A_cell the cell's area in the (rho, h) quadrant (2-D) or its volume of
- * revolution about the normal axis (3-D).  out = {E_MBR, E_Tangent}. */
+ * revolution about the normal axis (3-D).  out = {E_MBR, E_Tangent}.
+ * Parity unpinned beyond 0 < E_Tangent < E_MBR: the paper prints no value
+ * of either bound for a scene that can be rebuilt here. */
 void vo_error_bounds(const vo_cells *c, int dim, double *out)
 {
     double E[2] = {0.0, 0.0};
