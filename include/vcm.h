@@ -203,6 +203,57 @@ typedef struct {
 vcm_status vcm_compute(const vcm_index *index, const vcm_query *query,
                        const vcm_result *result, void *stream, vcm_stats *stats);
 
+/* ---------------------------------------------------------------- batches --- */
+
+/* Many queries on one index (each query is a Def. 2.1 problem of its own;
+ * batching changes how they are scheduled, never their results).  The
+ * queries' work is one persistent launch per group of queries that share a
+ * precision and a mode, so that maps of very different sizes fill the device
+ * together.  queries[i] writes results[i]; every result is bit-identical to
+ * what vcm_compute gives for that query alone.  Result buffers must not
+ * overlap.  Enqueues on `stream` and returns; with stats non-NULL it waits
+ * and reports counters summed over the batch. */
+vcm_status vcm_compute_batch(const vcm_index *index, const vcm_query *queries, int32_t nq,
+                             const vcm_result *results, void *stream, vcm_stats *stats);
+
+/* A prepared batch: validated queries, their device records and (optionally)
+ * the launch sequence captured as a HIP graph, replayed by vcm_batch_run.
+ * The queries and result pointers are fixed at creation. */
+typedef struct vcm_batch vcm_batch;
+
+typedef struct {
+    int32_t chunk;          /* viewpoints per work item, 1..64; 0 = default 8 */
+    int32_t blocks_per_cu;  /* persistent workgroups per CU, 1..16; 0 = default 8 */
+    int32_t autotune;       /* 1: at creation, time the candidate shapes
+                               (chunk 4/8/16/32 x 4/8 workgroups per CU) on a
+                               sample of the queries and keep the fastest;
+                               an explicit chunk or blocks_per_cu wins.  This
+                               runs the kernels and writes result buffers.  */
+    int32_t use_graph;      /* 1: capture the launches in a HIP graph         */
+} vcm_batch_opts;
+
+typedef struct {
+    int32_t chunk;
+    int32_t blocks_per_cu;
+    int32_t launches;       /* persistent ray launches per run              */
+    int32_t graph;          /* 1 if runs replay a captured graph            */
+    uint64_t viewpoints;
+    uint64_t work_items;
+    size_t device_bytes;    /* records, counters and block gates            */
+    double tune_ms;         /* host time spent autotuning                   */
+} vcm_batch_info;
+
+/* Create a batch (blocking; allocates its device buffer).  opts may be NULL. */
+vcm_status vcm_batch_create(const vcm_index *index, const vcm_query *queries, int32_t nq,
+                            const vcm_result *results, const vcm_batch_opts *opts,
+                            vcm_batch **out);
+/* Enqueue one run of the batch on `stream`.  Runs of one batch must not
+ * overlap (they share counters and outputs); order them on one stream. */
+vcm_status vcm_batch_run(vcm_batch *batch, void *stream);
+vcm_status vcm_batch_get_info(const vcm_batch *batch, vcm_batch_info *info);
+/* Wait for the device, then release the batch. */
+vcm_status vcm_batch_destroy(vcm_batch *batch);
+
 /* Approximation error of Sec. V-A between two colour maps of n viewpoints
  * (caller-owned device buffers, one float each), every viewpoint standing
  * for the same area:  out[0] = sum(c_exact - c_approx) / sum(c_exact)

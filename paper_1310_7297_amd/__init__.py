@@ -27,7 +27,9 @@ VCM_FP32_RECHECK, VCM_FP64 = 0, 1
 
 # Every symbol include/vcm.h declares.
 EXPORTS = ("vcm_last_error", "vcm_version", "vcm_build_index", "vcm_free_index",
-           "vcm_index_get_info", "vcm_compute", "vcm_map_error", "vcm_error_bounds")
+           "vcm_index_get_info", "vcm_compute", "vcm_compute_batch", "vcm_batch_create",
+           "vcm_batch_run", "vcm_batch_get_info", "vcm_batch_destroy", "vcm_map_error",
+           "vcm_error_bounds")
 
 
 class VcmError(RuntimeError):
@@ -90,6 +92,18 @@ class vcm_result(ctypes.Structure):
     _fields_ = [("bin", ctypes.c_void_p), ("c", ctypes.c_void_p), ("count", ctypes.c_void_p)]
 
 
+class vcm_batch_opts(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class vcm_batch_info(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("launches", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("viewpoints", ctypes.c_uint64), ("work_items", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_size_t), ("tune_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -121,8 +135,18 @@ def load_library(path: Optional[str] = None):
                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_double * 2)]
     L.vcm_error_bounds.argtypes = [ctypes.POINTER(vcm_query), ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_double * 2)]
+    L.vcm_compute_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_query), ctypes.c_int32,
+                                    ctypes.POINTER(vcm_result), ctypes.c_void_p,
+                                    ctypes.POINTER(vcm_stats)]
+    L.vcm_batch_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_query), ctypes.c_int32,
+                                   ctypes.POINTER(vcm_result), ctypes.POINTER(vcm_batch_opts),
+                                   ctypes.POINTER(ctypes.c_void_p)]
+    L.vcm_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    L.vcm_batch_get_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_batch_info)]
+    L.vcm_batch_destroy.argtypes = [ctypes.c_void_p]
     for name in ("vcm_build_index", "vcm_free_index", "vcm_index_get_info", "vcm_compute",
-                 "vcm_map_error", "vcm_error_bounds"):
+                 "vcm_compute_batch", "vcm_batch_create", "vcm_batch_run", "vcm_batch_get_info",
+                 "vcm_batch_destroy", "vcm_map_error", "vcm_error_bounds"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -253,6 +277,78 @@ def vcm_compute(index: Index, query: scenes.Query, bin_out, c_out=None, count_ou
     if stats:
         return {f: getattr(st, f) for f, _ in vcm_stats._fields_}
     return None
+
+
+def _make_result(n, bin_out, c_out=None, count_out=None) -> vcm_result:
+    for t, name in ((bin_out, "bin"), (c_out, "c"), (count_out, "count")):
+        if t is not None:
+            if not t.is_cuda or t.numel() < n or not t.is_contiguous():
+                raise ValueError(f"{name}: need a contiguous device tensor of >= {n} entries")
+    return vcm_result(bin_out.data_ptr(), c_out.data_ptr() if c_out is not None else None,
+                      count_out.data_ptr() if count_out is not None else None)
+
+
+def _batch_arrays(queries, results, precision):
+    nq = len(queries)
+    if len(results) != nq:
+        raise ValueError("one result triple per query")
+    if isinstance(precision, int):
+        precision = [precision] * nq
+    Qs = (vcm_query * max(nq, 1))()
+    Rs = (vcm_result * max(nq, 1))()
+    for i, (q, r) in enumerate(zip(queries, results)):
+        Qs[i] = make_query(q, precision[i])
+        Rs[i] = _make_result(q.grid.count, *r)
+    return Qs, Rs
+
+
+def _stats_dict(st: vcm_stats):
+    return {f: getattr(st, f) for f, _ in vcm_stats._fields_}
+
+
+def vcm_compute_batch(index: Index, queries, results, stream=None, stats: bool = False,
+                      precision=VCM_FP32_RECHECK):
+    """Enqueue many VCMs over one index; results[i] = (bin, c, count) tensors."""
+    L = load_library()
+    Qs, Rs = _batch_arrays(queries, results, precision)
+    st = vcm_stats()
+    _check(L.vcm_compute_batch(index.handle, Qs, len(queries), Rs, _stream_ptr(stream),
+                               ctypes.byref(st) if stats else None))
+    return _stats_dict(st) if stats else None
+
+
+class Batch:
+    """A prepared batch (vcm_batch_create); run() enqueues one replay."""
+
+    def __init__(self, index: Index, queries, results, chunk: int = 0, blocks_per_cu: int = 0,
+                 autotune: bool = False, use_graph: bool = True, precision=VCM_FP32_RECHECK):
+        L = load_library()
+        self._keep = (index, results)  # buffers must outlive the batch
+        Qs, Rs = _batch_arrays(queries, results, precision)
+        opts = vcm_batch_opts(int(chunk), int(blocks_per_cu), int(bool(autotune)), int(bool(use_graph)))
+        h = ctypes.c_void_p()
+        _check(L.vcm_batch_create(index.handle, Qs, len(queries), Rs, ctypes.byref(opts),
+                                  ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, stream=None):
+        _check(load_library().vcm_batch_run(self.handle, _stream_ptr(stream)))
+
+    def info(self):
+        i = vcm_batch_info()
+        _check(load_library().vcm_batch_get_info(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in vcm_batch_info._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(load_library().vcm_batch_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def vcm_map_error(c_exact, c_approx, stream=None):

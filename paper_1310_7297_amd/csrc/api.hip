@@ -8,10 +8,6 @@
 
 #include "vcm_internal.h"
 
-struct vcm_index {
-    vcm::Index impl;
-};
-
 namespace vcm {
 
 static thread_local std::string g_err;
@@ -30,18 +26,6 @@ bool dyadic(double x) {
     const double y = x * 256.0;
     return std::isfinite(y) && std::fabs(x) < kLimit && y == std::floor(y);
 }
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
-    }
-};
 
 double deg2rad(double d) { return d * M_PI / 180.0; }
 
@@ -200,7 +184,8 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
 
 vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
                      int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats) {
-    if (method == VCM_BRUTE) return launch_brute(ix, t, g, p, r, s, stats);
+    const Tuning tune{};
+    if (method == VCM_BRUTE) return launch_brute(ix, t, g, p, r, s, stats, nullptr, 1, tune);
     // pruned: gate at the block representatives, then the cell colours
     int32_t gn[3];
     int64_t nrep = 1;
@@ -211,7 +196,7 @@ vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, co
     uint32_t *gate = nullptr;
     hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&gate), sizeof(uint32_t) * nrep, s);
     if (e != hipSuccess) return set_error(VCM_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
-    vcm_status st = launch_brute(ix, t, g, p, r, s, stats, gate, theta);
+    vcm_status st = launch_brute(ix, t, g, p, r, s, stats, gate, theta, tune);
     if (st == VCM_OK)
         st = launch_pruned(ix, t, g, p, method, theta, gate, gn, r, s,
                            stats ? &stats->t_fallbacks : nullptr);

@@ -446,129 +446,200 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     return vis;
 }
 
-constexpr int kChunk = 8;  // consecutive viewpoints of one grid row per work item
+// Work items are kXcd contiguous ranges of the item list.  Workgroups are
+// dispatched to the XCDs in round-robin order, so a wavefront first drains
+// the range of its own XCD and then helps the others: neighbouring items are
+// then written through the same L2, which merges their partial cache lines
+// before they reach HBM.  Every range counter only grows, so each wavefront
+// leaves after at most kXcd exhausted ranges.
+__device__ inline unsigned range_begin(unsigned n, int r) {
+    return static_cast<unsigned>((static_cast<unsigned long long>(n) * r) / kXcd);
+}
 
-// Persistent wavefronts take work items (kChunk viewpoints of one row) from a
-// device counter; each viewpoint is traced by the whole wavefront, and the
-// chunk's results are written by kChunk lanes at once.
+__device__ inline bool next_item(unsigned *ctr, unsigned n_items, int &r, int &left,
+                                 unsigned &item) {
+    const int lane = threadIdx.x & 63;
+    while (left > 0) {
+        const unsigned b = range_begin(n_items, r), e = range_begin(n_items, r + 1);
+        unsigned i = 0;
+        if (lane == 0) i = atomicAdd(&ctr[r], 1u);
+        i = __builtin_amdgcn_readfirstlane(__shfl(i, 0));
+        if (i < e - b) {
+            item = b + i;
+            return true;
+        }
+        r = (r + 1) % kXcd;
+        --left;
+    }
+    return false;
+}
+
+// One work item of a query: A.chunk consecutive viewpoints of one grid row,
+// each traced by the whole wavefront; the results are written by A.chunk
+// lanes at once.  `item` counts from the start of the query's items.
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
+__device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &A, cptr_i32 col_start,
+                                                               cptr_rec recs, unsigned item, int *lds,
+                                                               WaveStats &ws,
+                                                               unsigned long long &n_disagree) {
+    using R = typename std::conditional<EXACT64, double, float>::type;
+    const int lane = threadIdx.x & 63;
+    const TargetDesc &T = A.tgt;
+    const ParamDesc &P = A.prm;
+    const int n0 = A.grid.n[0], n1 = A.grid.n[1];
+    const int chunk = A.chunk;
+    const int cpr = (n0 + chunk - 1) / chunk;
+    const int row = static_cast<int>(item / static_cast<unsigned>(cpr));
+    const int x0 = static_cast<int>(item - static_cast<unsigned>(row) * cpr) * chunk;
+    const int jj = row % n1, kk = A.k_begin + row / n1;
+    const int nv = min(chunk, n0 - x0);
+    const int64_t v0 = x0 + static_cast<int64_t>(n0) * (jj + static_cast<int64_t>(n1) * kk);
+    uint8_t o_bin = 0;
+    float o_c = 0.0f;
+    uint16_t o_cnt = 0;
+    uint32_t o_gate = 0;
+    for (int t = 0; t < nv; ++t) {
+        // grid index; in gate mode the launch grid is the block grid and
+        // each block is represented by its lowest-index centre viewpoint
+        int ii[3] = {x0 + t, jj, kk};
+        if (A.gate) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                ii[k] = min(ii[k] * A.theta + (A.theta - 1) / 2, A.full_n[k] - 1);
+        }
+        float q[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            q[k] = (k < DIM) ? A.grid.o[k] + static_cast<float>(2 * ii[k] + 1) * A.grid.h2[k] : 0.0f;
+        // live facets packed 4 bits each: cube faces whose outer side
+        // contains q strictly (code 2k+1 for +k, 2k for -k)
+        unsigned faces = 0;
+        int nf = 0;
+        if (T.kind == VCM_CUBE) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const bool up = q[k] > T.c[k] + T.half[k];
+                const bool dn = q[k] < T.c[k] - T.half[k];
+                if (up || dn) {
+                    faces |= static_cast<unsigned>(2 * k + (up ? 1 : 0)) << (4 * nf);
+                    ++nf;
+                }
+            }
+        } else {
+            nf = 1;
+        }
+        const int N = nf * T.per_facet;
+        const bool fov = in_fov<DIM>(T, P, q);
+        int cnt = 0;
+        R col = R(0);
+        if (fov && N > 0) {
+            if (STATS) ws.rays += N;
+            const int vis = trace_viewpoint<DIM, NS, EXACT64, MODE, STATS>(A, col_start, recs, q, faces,
+                                                                            N, lds, ws, n_disagree);
+            if (MODE == VCM_FRACTION) {
+                cnt = vis;
+                if (vis > 0) col = (R(vis) / R(N)) * raw_colour<DIM, R>(T, P, q);
+            } else if (vis == N) {
+                cnt = N;
+                col = raw_colour<DIM, R>(T, P, q);
+            }
+        }
+        R cb = col;
+        if (P.bin_scale == VCM_BIN_LOG) {
+            const R veff = col * R(P.V0);
+            cb = veff <= R(P.mu) ? R(0) : fmin(R(1), log(veff / R(P.mu)) * R(P.inv_log_V0_mu));
+        }
+        const int bn = min(P.n_bins - 1, static_cast<int>(floor(cb * R(P.n_bins))));
+        if (lane == t) {
+            o_bin = static_cast<uint8_t>(bn);
+            o_c = static_cast<float>(col);
+            o_cnt = static_cast<uint16_t>(cnt);
+            o_gate = static_cast<uint32_t>(cnt) | (static_cast<uint32_t>(N) << 10) |
+                     (fov ? (1u << 20) : 0u);
+        }
+    }
+    if (lane < nv) {
+        if (A.gate) {
+            A.gate[v0 + lane] = o_gate;
+        } else {
+            A.bin[v0 + lane] = o_bin;
+            if (A.c) A.c[v0 + lane] = o_c;
+            if (A.count) A.count[v0 + lane] = o_cnt;
+        }
+    }
+}
+
+template <bool STATS>
+__device__ inline void flush_stats(DevStats *st, const WaveStats &ws, unsigned long long n_disagree) {
+    if (!STATS) return;
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&st->rays, ws.rays);
+        atomicAdd(&st->box_tests, ws.tests);
+        atomicAdd(&st->slot_tests, ws.slots);
+        atomicAdd(&st->rechecks, ws.rechecks);
+        atomicAdd(&st->columns, ws.cols);
+        atomicAdd(&st->inside_box, ws.inside);
+    }
+    if (n_disagree) atomicAdd(&st->fp32_disagree, n_disagree);  // per lane
+}
+
+// One query: persistent wavefronts take the query's work items.
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_brute(BruteArgs A, const int32_t *col_start_g,
                                                const BoxRec *recs_g) {
     // same kernel symbol in both compiler passes; constant-space view inside
     const cptr_i32 col_start = (cptr_i32)col_start_g;
     const cptr_rec recs = (cptr_rec)recs_g;
-    using R = typename std::conditional<EXACT64, double, float>::type;
     __shared__ int lds_rays[4][kMaxSamples];
-    const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int *lds = lds_rays[wave];
-    const TargetDesc &T = A.tgt;
-    const ParamDesc &P = A.prm;
-    const int n0 = A.grid.n[0], n1 = A.grid.n[1];
-    const int cpr = (n0 + kChunk - 1) / kChunk;
     WaveStats ws;
     unsigned long long n_disagree = 0;
+    int r = blockIdx.x % kXcd, left = kXcd;
+    unsigned item;
+    while (next_item(A.counter, A.n_items, r, left, item))
+        run_item<DIM, NS, EXACT64, MODE, STATS>(A, col_start, recs, item, lds, ws, n_disagree);
+    flush_stats<STATS>(A.stats, ws, n_disagree);
+}
 
-    for (;;) {
-        unsigned item = 0;
-        if (lane == 0) item = atomicAdd(A.counter, 1u);
-        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
-        if (item >= A.n_items) break;
-        const int row = static_cast<int>(item / static_cast<unsigned>(cpr));
-        const int x0 = static_cast<int>(item - static_cast<unsigned>(row) * cpr) * kChunk;
-        const int jj = row % n1, kk = A.k_begin + row / n1;
-        const int nv = min(kChunk, n0 - x0);
-        const int64_t v0 = x0 + static_cast<int64_t>(n0) * (jj + static_cast<int64_t>(n1) * kk);
-        uint8_t o_bin = 0;
-        float o_c = 0.0f;
-        uint16_t o_cnt = 0;
-        uint32_t o_gate = 0;
-        for (int t = 0; t < nv; ++t) {
-            // grid index; in gate mode the launch grid is the block grid and
-            // each block is represented by its lowest-index centre viewpoint
-            int ii[3] = {x0 + t, jj, kk};
-            if (A.gate) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    ii[k] = min(ii[k] * A.theta + (A.theta - 1) / 2, A.full_n[k] - 1);
-            }
-            float q[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                q[k] = (k < DIM) ? A.grid.o[k] + static_cast<float>(2 * ii[k] + 1) * A.grid.h2[k] : 0.0f;
-            // live facets packed 4 bits each: cube faces whose outer side
-            // contains q strictly (code 2k+1 for +k, 2k for -k)
-            unsigned faces = 0;
-            int nf = 0;
-            if (T.kind == VCM_CUBE) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const bool up = q[k] > T.c[k] + T.half[k];
-                    const bool dn = q[k] < T.c[k] - T.half[k];
-                    if (up || dn) {
-                        faces |= static_cast<unsigned>(2 * k + (up ? 1 : 0)) << (4 * nf);
-                        ++nf;
-                    }
-                }
-            } else {
-                nf = 1;
-            }
-            const int N = nf * T.per_facet;
-            const bool fov = in_fov<DIM>(T, P, q);
-            int cnt = 0;
-            R col = R(0);
-            if (fov && N > 0) {
-                if (STATS) ws.rays += N;
-                const int vis =
-                    trace_viewpoint<DIM, NS, EXACT64, MODE, STATS>(A, col_start, recs, q, faces, N, lds, ws,
-                                                                    n_disagree);
-                if (MODE == VCM_FRACTION) {
-                    cnt = vis;
-                    if (vis > 0) col = (R(vis) / R(N)) * raw_colour<DIM, R>(T, P, q);
-                } else if (vis == N) {
-                    cnt = N;
-                    col = raw_colour<DIM, R>(T, P, q);
-                }
-            }
-            R cb = col;
-            if (P.bin_scale == VCM_BIN_LOG) {
-                const R veff = col * R(P.V0);
-                cb = veff <= R(P.mu) ? R(0) : fmin(R(1), log(veff / R(P.mu)) * R(P.inv_log_V0_mu));
-            }
-            const int bn = min(P.n_bins - 1, static_cast<int>(floor(cb * R(P.n_bins))));
-            if (lane == t) {
-                o_bin = static_cast<uint8_t>(bn);
-                o_c = static_cast<float>(col);
-                o_cnt = static_cast<uint16_t>(cnt);
-                o_gate = static_cast<uint32_t>(cnt) | (static_cast<uint32_t>(N) << 10) |
-                         (fov ? (1u << 20) : 0u);
-            }
+// Many queries on one index in one launch.  The work items of all queries
+// form one list (query after query); a wavefront finds the query of an item
+// by binary search over the queries' item ends and reads the query's record
+// from constant memory (scalar loads).
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_brute_batch(
+    BatchArgs B, const BruteArgs *qs_g, const uint32_t *item_end_g, const int32_t *col_start_g,
+    const BoxRec *recs_g) {
+    const cptr_i32 col_start = (cptr_i32)col_start_g;
+    const cptr_rec recs = (cptr_rec)recs_g;
+    const VCM_CONST BruteArgs *qs = (const VCM_CONST BruteArgs *)qs_g;
+    const VCM_CONST uint32_t *item_end = (const VCM_CONST uint32_t *)item_end_g;
+    __shared__ int lds_rays[4][kMaxSamples];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int *lds = lds_rays[wave];
+    WaveStats ws;
+    unsigned long long n_disagree = 0;
+    int r = blockIdx.x % kXcd, left = kXcd;
+    unsigned item;
+    while (next_item(B.counter, B.n_items, r, left, item)) {
+        int lo = 0, hi = B.nq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (item_end[mid] > item) hi = mid;
+            else lo = mid + 1;
         }
-        if (lane < nv) {
-            if (A.gate) {
-                A.gate[v0 + lane] = o_gate;
-            } else {
-                A.bin[v0 + lane] = o_bin;
-                if (A.c) A.c[v0 + lane] = o_c;
-                if (A.count) A.count[v0 + lane] = o_cnt;
-            }
-        }
+        const unsigned begin = lo > 0 ? item_end[lo - 1] : 0u;
+        // a generic reference derived from the constant-space pointer: the
+        // compiler turns the field reads back into scalar constant loads
+        // (a local copy of the record would live in scratch memory)
+        const BruteArgs &A = *reinterpret_cast<const BruteArgs *>(qs + lo);
+        run_item<DIM, NS, EXACT64, MODE, STATS>(A, col_start, recs, item - begin, lds, ws, n_disagree);
     }
-    if (STATS) {
-        if (lane == 0) {
-            atomicAdd(&A.stats->rays, ws.rays);
-            atomicAdd(&A.stats->box_tests, ws.tests);
-            atomicAdd(&A.stats->slot_tests, ws.slots);
-            atomicAdd(&A.stats->rechecks, ws.rechecks);
-            atomicAdd(&A.stats->columns, ws.cols);
-            atomicAdd(&A.stats->inside_box, ws.inside);
-        }
-        if (n_disagree) atomicAdd(&A.stats->fp32_disagree, n_disagree);  // per lane
-    }
+    flush_stats<STATS>(B.stats, ws, n_disagree);
 }
 
 __global__ void k_zero_counter(unsigned *c) {
-    if (threadIdx.x == 0) *c = 0u;
+    if (threadIdx.x < kXcd) c[threadIdx.x] = 0u;
 }
 
 struct Launch {
@@ -577,35 +648,55 @@ struct Launch {
     hipStream_t st;
 };
 
-template <int DIM, int NS, bool EXACT64, int MODE>
-void launch_mode(const BruteArgs &a, const Launch &L) {
-    if (L.stats)
-        hipLaunchKernelGGL((k_brute<DIM, NS, EXACT64, MODE, true>), L.grid, dim3(256), 0, L.st, a,
-                           a.idx.col_start, a.idx.recs);
-    else
-        hipLaunchKernelGGL((k_brute<DIM, NS, EXACT64, MODE, false>), L.grid, dim3(256), 0, L.st, a,
-                           a.idx.col_start, a.idx.recs);
-}
+// Compile-time variant of the ray kernels.
+template <int DIM_, int NS_, bool E_, int MODE_, bool ST_>
+struct Variant {
+    static constexpr int DIM = DIM_, NS = NS_, MODE = MODE_;
+    static constexpr bool E = E_, ST = ST_;
+};
 
-template <int DIM, int NS, bool EXACT64>
-void launch_ns(const BruteArgs &a, const Launch &L) {
-    if (a.prm.mode == VCM_FULL)
-        launch_mode<DIM, NS, EXACT64, VCM_FULL>(a, L);
-    else
-        launch_mode<DIM, NS, EXACT64, VCM_FRACTION>(a, L);
+template <int DIM, int NS, bool E, int MODE, class F>
+void dispatch_stats(bool stats, F &&f) {
+    if (stats) f(Variant<DIM, NS, E, MODE, true>{});
+    else f(Variant<DIM, NS, E, MODE, false>{});
 }
-
-template <int DIM, bool EXACT64>
-void launch_dim(const BruteArgs &a, int ns, const Launch &L) {
+template <int DIM, int NS, bool E, class F>
+void dispatch_mode(int mode, bool stats, F &&f) {
+    if (mode == VCM_FULL) dispatch_stats<DIM, NS, E, VCM_FULL>(stats, f);
+    else dispatch_stats<DIM, NS, E, VCM_FRACTION>(stats, f);
+}
+// Solo launches: a kernel per slot count.
+template <int DIM, bool E, class F>
+void dispatch_ns_all(int ns, int mode, bool stats, F &&f) {
     switch (ns) {
-        case 1: launch_ns<DIM, 1, EXACT64>(a, L); break;
-        case 2: launch_ns<DIM, 2, EXACT64>(a, L); break;
-        case 3: launch_ns<DIM, 3, EXACT64>(a, L); break;
-        case 4: launch_ns<DIM, 4, EXACT64>(a, L); break;
-        case 5: launch_ns<DIM, 5, EXACT64>(a, L); break;
-        default: launch_ns<DIM, 6, EXACT64>(a, L); break;
+        case 1: dispatch_mode<DIM, 1, E>(mode, stats, f); break;
+        case 2: dispatch_mode<DIM, 2, E>(mode, stats, f); break;
+        case 3: dispatch_mode<DIM, 3, E>(mode, stats, f); break;
+        case 4: dispatch_mode<DIM, 4, E>(mode, stats, f); break;
+        case 5: dispatch_mode<DIM, 5, E>(mode, stats, f); break;
+        default: dispatch_mode<DIM, 6, E>(mode, stats, f); break;
     }
 }
+// Batched launches: slot counts rounded up to 2, 3 or 6 (empty slots cost a
+// scalar branch per box).
+template <int DIM, bool E, class F>
+void dispatch_ns_batch(int ns, int mode, bool stats, F &&f) {
+    if (ns <= 2) dispatch_mode<DIM, 2, E>(mode, stats, f);
+    else if (ns == 3) dispatch_mode<DIM, 3, E>(mode, stats, f);
+    else dispatch_mode<DIM, 6, E>(mode, stats, f);
+}
+template <bool BATCH, class F>
+void dispatch(int dim, bool fp64, int ns, int mode, bool stats, F &&f) {
+    if (dim == 2) {
+        if (fp64) BATCH ? dispatch_ns_batch<2, true>(ns, mode, stats, f) : dispatch_ns_all<2, true>(ns, mode, stats, f);
+        else BATCH ? dispatch_ns_batch<2, false>(ns, mode, stats, f) : dispatch_ns_all<2, false>(ns, mode, stats, f);
+    } else {
+        if (fp64) BATCH ? dispatch_ns_batch<3, true>(ns, mode, stats, f) : dispatch_ns_all<3, true>(ns, mode, stats, f);
+        else BATCH ? dispatch_ns_batch<3, false>(ns, mode, stats, f) : dispatch_ns_all<3, false>(ns, mode, stats, f);
+    }
+}
+
+}  // namespace
 
 int device_cus(int device) {
     static int cached[64] = {0};
@@ -619,12 +710,14 @@ int device_cus(int device) {
     return cached[device];
 }
 
-}  // namespace
+int slots_for(const TargetDesc &t) {
+    const int max_n = t.per_facet * (t.kind == VCM_CUBE ? 3 : 1);
+    return (max_n + 63) / 64;
+}
 
-vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_in,
-                        const ParamDesc &p, const vcm_result &r, hipStream_t stream,
-                        DevStats *stats, uint32_t *gate, int theta) {
-    if (g_in.count <= 0) return VCM_OK;
+BruteArgs make_brute_args(const Index &ix, const TargetDesc &t, const GridDesc &g_in,
+                          const ParamDesc &p, const vcm_result &r, uint32_t *gate, int theta,
+                          int chunk) {
     BruteArgs a{};
     GridDesc g = g_in;
     a.theta = theta;
@@ -645,18 +738,48 @@ vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_
     a.bin = r.bin;
     a.c = r.c;
     a.count = r.count;
+    a.chunk = chunk;
+    a.k_begin = 0;
+    const uint64_t cpr = (static_cast<uint64_t>(g.n[0]) + chunk - 1) / chunk;
+    const uint64_t items = cpr * static_cast<uint64_t>(g.n[1]) * static_cast<uint64_t>(g.n[2]);
+    a.n_items = items > 0xffffffffull ? 0xffffffffu : static_cast<uint32_t>(items);
+    return a;
+}
+
+void launch_zero_counter(unsigned *c, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, c);
+}
+
+vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, const BatchArgs &b,
+                              const BruteArgs *d_recs, const uint32_t *d_item_end, int blocks,
+                              hipStream_t s) {
+    if (b.n_items == 0) return VCM_OK;
+    launch_zero_counter(b.counter, s);
+    const dim3 grid(static_cast<unsigned>(blocks));
+    dispatch<true>(ix.dim, fp64, ns, mode, b.stats != nullptr, [&](auto v) {
+        using V = decltype(v);
+        hipLaunchKernelGGL((k_brute_batch<V::DIM, V::NS, V::E, V::MODE, V::ST>), grid, dim3(256), 0, s, b,
+                           d_recs, d_item_end, ix.dev.col_start, ix.dev.recs);
+    });
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(VCM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return VCM_OK;
+}
+
+vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_in,
+                        const ParamDesc &p, const vcm_result &r, hipStream_t stream,
+                        DevStats *stats, uint32_t *gate, int theta, const Tuning &tune) {
+    if (g_in.count <= 0) return VCM_OK;
+    BruteArgs a = make_brute_args(ix, t, g_in, p, r, gate, theta, tune.chunk);
     a.stats = stats;
-    const int max_n = t.per_facet * (t.kind == VCM_CUBE ? 3 : 1);
-    const int ns = (max_n + 63) / 64;
+    const int ns = slots_for(t);
     if (ns < 1 || ns > kMaxSlots) return set_error(VCM_E_INVALID, "too many target samples");
     unsigned *counter = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&counter), sizeof(unsigned), stream);
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&counter), sizeof(unsigned) * kXcd, stream);
     if (e != hipSuccess) return set_error(VCM_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     a.counter = counter;
-    Launch L;
-    L.stats = stats != nullptr;
-    L.st = stream;
-    const int64_t cpr = (g.n[0] + kChunk - 1) / kChunk;
+    const GridDesc &g = a.grid;
+    const int64_t cpr = (g.n[0] + a.chunk - 1) / a.chunk;
     const int64_t rows_per_layer = g.n[1];
     // launches over z slabs keep the work-item count within 32 bits
     const int64_t max_layers = std::max<int64_t>(1, (int64_t(1) << 30) / (cpr * rows_per_layer));
@@ -665,16 +788,14 @@ vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_
         const int64_t nl = std::min<int64_t>(max_layers, g.n[2] - k0);
         a.k_begin = static_cast<int32_t>(k0);
         a.n_items = static_cast<unsigned>(cpr * rows_per_layer * nl);
-        const int64_t blocks = std::min<int64_t>((a.n_items + 3) / 4, int64_t(cus) * 8);
-        L.grid = dim3(static_cast<unsigned>(blocks));
-        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, counter);
-        if (ix.dim == 2) {
-            if (p.fp64) launch_dim<2, true>(a, ns, L);
-            else launch_dim<2, false>(a, ns, L);
-        } else {
-            if (p.fp64) launch_dim<3, true>(a, ns, L);
-            else launch_dim<3, false>(a, ns, L);
-        }
+        const int64_t blocks = std::min<int64_t>((a.n_items + 3) / 4, int64_t(cus) * tune.blocks_per_cu);
+        const dim3 grid(static_cast<unsigned>(blocks));
+        launch_zero_counter(counter, stream);
+        dispatch<false>(ix.dim, p.fp64 != 0, ns, p.mode, stats != nullptr, [&](auto v) {
+            using V = decltype(v);
+            hipLaunchKernelGGL((k_brute<V::DIM, V::NS, V::E, V::MODE, V::ST>), grid, dim3(256), 0, stream, a,
+                               a.idx.col_start, a.idx.recs);
+        });
         e = hipGetLastError();
         if (e != hipSuccess) {
             hipFreeAsync(counter, stream);

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "vcm.h"
 
@@ -18,6 +20,9 @@ constexpr float kFatMargin = 1.0f / 64.0f;
 // Largest number of live samples per viewpoint (64-lane slots x 6).
 constexpr int kMaxSamples = 384;
 constexpr int kMaxSlots = 6;
+
+// XCDs of an MI355X; work-item lists are split into this many ranges.
+constexpr int kXcd = 8;
 
 // One box reference inside a column list (32 bytes, one scalar load).
 // Coordinates are in the index frame (see DevIndex), where they are >= 0,
@@ -109,12 +114,28 @@ struct BruteArgs {
     float *c;
     uint16_t *count;
     DevStats *stats;
-    unsigned *counter;  // work-item counter (zeroed before the launch)
+    unsigned *counter;  // kXcd work-item range counters (zeroed before the launch)
     uint32_t *gate;     // gate mode: per block, count | N << 10 | fov << 20
     int32_t theta;      // block size in viewpoints (gate mode)
     int32_t full_n[3];  // the viewpoint grid (gate mode)
     int32_t k_begin;    // first z layer of this launch
     uint32_t n_items;   // work items in this launch
+    int32_t chunk;      // viewpoints of one grid row per work item (1..64)
+    int32_t pad;
+};
+
+// A launch over the work items of many queries.
+struct BatchArgs {
+    unsigned *counter;  // kXcd range counters
+    DevStats *stats;
+    int32_t nq;
+    uint32_t n_items;
+};
+
+// Launch shape of the ray kernels.
+struct Tuning {
+    int chunk = 8;          // viewpoints per work item
+    int blocks_per_cu = 8;  // persistent workgroups (4 wavefronts each) per CU
 };
 
 // Host-side index object behind the opaque vcm_index handle.
@@ -133,6 +154,19 @@ struct Index {
     std::string scene_key;
 };
 
+// Makes `dev` current for the lifetime of the guard.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
 // Thread-local error reporting.
 vcm_status set_error(vcm_status st, const std::string &msg);
 void clear_error();
@@ -141,10 +175,22 @@ void clear_error();
 vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, GridDesc *g,
                          ParamDesc *p);
 
-// Launch the brute-force kernel over [vp_begin, vp_end) on `stream`.
+// Launch the brute-force kernel over the whole grid of one query on `stream`
+// (gate mode: over the representatives of the theta-blocks).
 vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g,
                         const ParamDesc &p, const vcm_result &r, hipStream_t stream,
-                        DevStats *stats, uint32_t *gate = nullptr, int theta = 1);
+                        DevStats *stats, uint32_t *gate, int theta, const Tuning &tune);
+
+// Pieces of a batched launch.
+int device_cus(int device);
+int slots_for(const TargetDesc &t);
+BruteArgs make_brute_args(const Index &ix, const TargetDesc &t, const GridDesc &g,
+                          const ParamDesc &p, const vcm_result &r, uint32_t *gate, int theta,
+                          int chunk);
+void launch_zero_counter(unsigned *c, hipStream_t s);
+vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, const BatchArgs &b,
+                              const BruteArgs *d_recs, const uint32_t *d_item_end, int blocks,
+                              hipStream_t s);
 
 // Pruned colouring (E / M / T) of every viewpoint from the block gates.
 vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g,
@@ -160,8 +206,81 @@ void error_bounds(double S, double mu, double d0, int dim, double *out);
 vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
                      int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats);
 
+// Pinned host buffers for host-to-device uploads, reused once the copies
+// that read them have completed (tracked by an event per buffer).
+class Staging {
+  public:
+    vcm_status acquire(size_t bytes, int device, int *slot, void **ptr);
+    vcm_status release(int slot, hipStream_t s);
+
+  private:
+    static constexpr size_t kMaxSlotsStaging = 32;
+    struct Slot {
+        void *h = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        int device = -1;
+        bool busy = false;
+        bool pending = false;
+    };
+    std::mutex m_;
+    std::vector<Slot> slots_;
+};
+Staging &staging();
+// Copy `bytes` from host memory to device memory, ordered on `s`; the host
+// buffer may be reused as soon as the call returns.
+vcm_status upload(const void *src, size_t bytes, void *dst, int device, hipStream_t s);
+
+// One query of a batch, translated.
+struct PlanQuery {
+    TargetDesc t;
+    GridDesc g;
+    ParamDesc p;
+    int method;
+    int theta;
+    vcm_result r;
+    int ns;
+    int32_t gn[3];   // block grid (pruned methods)
+    int64_t nrep;    // blocks
+    size_t gate_off; // byte offset of the block gates in the plan's buffer
+};
+
+// Queries that share one persistent launch.
+struct PlanGroup {
+    bool fp64 = false;
+    int mode = 0;
+    int ns = 1;
+    std::vector<int> members;
+    size_t rec_off = 0, end_off = 0, ctr_off = 0;
+    uint32_t n_items = 0;
+};
+
+// Device layout and launch sequence of a batch:
+//   per group: BruteArgs[members] | item ends[members] | kXcd counters,
+//   then per pruned query its block gates.
+struct BatchPlan {
+    const Index *ix = nullptr;
+    int device = 0;
+    std::vector<PlanQuery> q;
+    std::vector<PlanGroup> groups;
+    Tuning tune;
+    size_t bytes = 0;        // device buffer
+    size_t image_bytes = 0;  // uploaded part (records, ends, counters)
+    char *d_base = nullptr;
+    uint64_t viewpoints = 0, items = 0;
+
+    vcm_status prepare(const Index &ix, const vcm_query *qs, int nq, const vcm_result *rs);
+    void layout();
+    void image(std::vector<char> &img) const;  // uses d_base
+    vcm_status enqueue(hipStream_t s, DevStats *stats) const;
+};
+
 // Build the column index on the device.
 vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, int64_t n,
                               double cell_size, hipStream_t stream);
 
 }  // namespace vcm
+
+struct vcm_index {
+    vcm::Index impl;
+};
