@@ -35,7 +35,11 @@ def parse():
     ap.add_argument("--cell", type=float, default=0.0)
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="time the headline map only (no other mode, batch or serving legs)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched (config 4) leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving (config 5) leg")
+    ap.add_argument("--serve-requests", type=int, default=240)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -71,6 +75,115 @@ def timed_steps(vcm, idx, q, bufs, steps, warmup):
     wall = time.perf_counter() - t0
     kms = [e0.elapsed_time(e1) for e0, e1 in evs]
     return wall, kms
+
+
+def bench_batch():
+    """Config 4: 256 targets on a shared 50,000-box city, grids 32x32x16 to
+    256x256x64.  One prepared batch (autotuned launch shape, HIP graph) against
+    the same 256 queries as sequential vcm_compute calls; results identical."""
+    import torch
+    import paper_1310_7297_amd as vcm
+    from paper_1310_7297_amd import scenes
+    scene, qs = scenes.config4()
+    idx = vcm.vcm_build_index(scene)
+    n_vp = sum(q.grid.count for q in qs)
+    seq = [vcm.alloc_result(q.grid.count) for q in qs]
+    res = [vcm.alloc_result(q.grid.count) for q in qs]
+    t0 = time.perf_counter()
+    b = vcm.Batch(idx, qs, res, autotune=True, use_graph=True)
+    create_s = time.perf_counter() - t0
+    info = b.info()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    def sequential():
+        for q, r in zip(qs, seq):
+            vcm.vcm_compute(idx, q, *r)
+
+    t_seq = timed(sequential, 2)
+    t_batch = timed(b.run, 3)
+    t_once = timed(lambda: vcm.vcm_compute_batch(idx, qs, res), 2)
+    torch.cuda.synchronize()
+    same = all(torch.equal(x, y) for a, r in zip(seq, res) for x, y in zip(a, r))
+    b.close()
+    idx.free()
+    return {"workload": "config4: 256 billboards/cubes (5-40 m), 50,000-box 6.4 km city, "
+                        "grids 32x32x16..256x256x64",
+            "viewpoints": n_vp, "sequential_viewpoints_per_s": n_vp / t_seq,
+            "batched_viewpoints_per_s": n_vp / t_batch,
+            "batched_unprepared_viewpoints_per_s": n_vp / t_once,
+            "speedup_vs_sequential": t_seq / t_batch, "identical_to_sequential": bool(same),
+            "chunk": info["chunk"], "blocks_per_cu": info["blocks_per_cu"],
+            "launches": info["launches"], "graph": bool(info["graph"]),
+            "create_s": create_s, "autotune_ms": info["tune_ms"]}
+
+
+def bench_serve(n_req: int):
+    """Config 5: Poisson arrivals over a resident 100,000-box 8 km city; grids
+    64x64x16 / 128x128x32 / 256x256x64 (0.6/0.3/0.1).  p50/p99 latency and
+    throughput per arrival rate, and the same requests as sequential calls."""
+    import threading
+    import torch
+    import paper_1310_7297_amd as vcm
+    from paper_1310_7297_amd import scenes
+    scene, qs = scenes.config5(n_requests=n_req)
+    idx = vcm.vcm_build_index(scene)
+    res = [vcm.alloc_result(q.grid.count) for q in qs]
+    n_vp = sum(q.grid.count for q in qs)
+    # sequential plain calls, back to back
+    for q, r in zip(qs[:8], res[:8]):
+        vcm.vcm_compute(idx, q, *r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, r in zip(qs, res):
+        vcm.vcm_compute(idx, q, *r)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    out = {"workload": "config5: 100,000-box 8 km city, Poisson arrivals, grids 64x64x16 / "
+                       "128x128x32 / 256x256x64 (0.6/0.3/0.1)",
+           "requests": n_req, "mean_viewpoints": n_vp / n_req,
+           "sequential_requests_per_s": n_req / t_seq, "rates": []}
+    srv = vcm.Server(idx, max_inflight=2, max_batch=64)
+    for rate in (100.0, 250.0, 500.0, 1000.0, 4000.0):
+        srv.reset_stats()
+        arr = scenes.poisson_arrivals(rate, n_req, 55)
+        tickets = []
+        t0 = time.perf_counter()
+
+        def submit():
+            for i, q in enumerate(qs):
+                while time.perf_counter() - t0 < arr[i]:
+                    time.sleep(0.0001)
+                while True:
+                    t = srv.submit(q, res[i])
+                    if t is not None:
+                        tickets.append(t)
+                        break
+                    time.sleep(0.0002)
+
+        th = threading.Thread(target=submit)
+        th.start()
+        th.join()
+        srv.drain()
+        for t in tickets:
+            srv.poll(t)
+        st = srv.stats()
+        out["rates"].append({"offered_req_per_s": rate, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                             "max_ms": st["max_ms"], "requests_per_s": st["requests_per_s"],
+                             "viewpoints_per_s": st["viewpoints_per_s"], "launches": st["launches"],
+                             "rejected_submits": st["rejected"], "mem_peak": st["mem_peak"]})
+        print(f"serve: offered {rate:.0f} req/s -> {st['requests_per_s']:.0f} req/s, "
+              f"p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+    srv.close()
+    idx.free()
+    return out
 
 
 def main():
@@ -133,6 +246,13 @@ def main():
         extra["other_mode"] = {"mode": "full" if mode == scenes.FRACTION else "fraction",
                                "viewpoints_per_s": n_vp * max(2, args.steps // 2) / w2,
                                "kernel_ms": float(np.mean(k2))}
+
+    if not (args.no_batch or args.no_extra):
+        extra["batch"] = bench_batch()
+        print(f"batch: {extra['batch']['speedup_vs_sequential']:.2f}x sequential", file=sys.stderr,
+              flush=True)
+    if not (args.no_serve or args.no_extra):
+        extra["serving"] = bench_serve(args.serve_requests)
 
     cpu = None
     if not args.no_cpu:

@@ -254,6 +254,70 @@ vcm_status vcm_batch_get_info(const vcm_batch *batch, vcm_batch_info *info);
 /* Wait for the device, then release the batch. */
 vcm_status vcm_batch_destroy(vcm_batch *batch);
 
+/* ---------------------------------------------------------------- serving --- */
+
+/* A server keeps an index resident and serves VCM queries submitted from any
+ * thread.  Admission is by device memory: a request's footprint is its result
+ * buffers (1 B bin + 4 B colour + 2 B count per viewpoint, for the buffers
+ * given), its work record and, for the pruned methods, 4 B per theta-block;
+ * a request is admitted while the footprints of all unfinished requests fit
+ * in mem_budget_bytes.  One engine thread batches the admitted requests as
+ * they arrive: whenever one of max_inflight launch slots (streams) is free it
+ * takes every waiting request, up to max_batch, into one batched launch
+ * (vcm_compute_batch), so launches overlap on the device.  Each result is
+ * bit-identical to vcm_compute of the same query alone.  The index must
+ * outlive the server; result buffers must stay valid until the request is
+ * finished (vcm_poll / vcm_wait returns other than VCM_E_PENDING). */
+typedef struct vcm_server vcm_server;
+
+typedef struct {
+    size_t mem_budget_bytes;  /* 0 = half of the device memory free at creation */
+    int32_t max_inflight;     /* launch slots, 1..8; 0 = 2                      */
+    int32_t max_batch;        /* requests per launch, 1..4096; 0 = 64           */
+    int32_t chunk;            /* launch shape as in vcm_batch_opts; 0 = default */
+    int32_t blocks_per_cu;
+} vcm_server_opts;
+
+typedef struct {
+    double latency_ms;        /* submit to completion seen by the engine      */
+    double queue_ms;          /* submit to launch                             */
+    uint64_t viewpoints;
+} vcm_request_info;
+
+typedef struct {
+    uint64_t completed, failed;
+    uint64_t rejected;        /* submits refused with VCM_E_AGAIN             */
+    uint64_t launches;
+    uint64_t viewpoints;      /* of completed requests                        */
+    double p50_ms, p99_ms, max_ms;   /* latency of completed requests (nearest rank) */
+    double requests_per_s;    /* completed / (last completion - first submit) */
+    double viewpoints_per_s;
+    size_t mem_in_use, mem_peak, mem_budget;
+} vcm_server_stats;
+
+vcm_status vcm_server_create(const vcm_index *index, const vcm_server_opts *opts,
+                             vcm_server **out);
+/* Validate and admit a query.  VCM_E_AGAIN: the budget is in use now, retry
+ * later (nothing was queued); VCM_E_INVALID: the query is invalid or larger
+ * than the whole budget.  On VCM_OK, *ticket names the request. */
+vcm_status vcm_submit(vcm_server *server, const vcm_query *query, const vcm_result *result,
+                      uint64_t *ticket);
+/* VCM_E_PENDING while the request runs.  Once it is finished, returns its
+ * status (VCM_OK, or the error that ended it) once, fills info if non-NULL,
+ * and forgets the ticket (later polls give VCM_E_NOTFOUND). */
+vcm_status vcm_poll(vcm_server *server, uint64_t ticket, vcm_request_info *info);
+/* vcm_poll after waiting up to timeout_ms (< 0: no limit) for the request. */
+vcm_status vcm_wait(vcm_server *server, uint64_t ticket, int32_t timeout_ms,
+                    vcm_request_info *info);
+/* Wait until every admitted request has finished. */
+vcm_status vcm_server_drain(vcm_server *server);
+vcm_status vcm_server_get_stats(vcm_server *server, vcm_server_stats *stats);
+vcm_status vcm_server_reset_stats(vcm_server *server);
+/* Stop the engine: requests not yet launched finish with VCM_E_INTERNAL
+ * (their buffers untouched), launches in flight are waited for; then the
+ * server is released and its tickets with it. */
+vcm_status vcm_server_destroy(vcm_server *server);
+
 /* Approximation error of Sec. V-A between two colour maps of n viewpoints
  * (caller-owned device buffers, one float each), every viewpoint standing
  * for the same area:  out[0] = sum(c_exact - c_approx) / sum(c_exact)

@@ -28,8 +28,9 @@ VCM_FP32_RECHECK, VCM_FP64 = 0, 1
 # Every symbol include/vcm.h declares.
 EXPORTS = ("vcm_last_error", "vcm_version", "vcm_build_index", "vcm_free_index",
            "vcm_index_get_info", "vcm_compute", "vcm_compute_batch", "vcm_batch_create",
-           "vcm_batch_run", "vcm_batch_get_info", "vcm_batch_destroy", "vcm_map_error",
-           "vcm_error_bounds")
+           "vcm_batch_run", "vcm_batch_get_info", "vcm_batch_destroy", "vcm_server_create",
+           "vcm_submit", "vcm_poll", "vcm_wait", "vcm_server_drain", "vcm_server_get_stats",
+           "vcm_server_reset_stats", "vcm_server_destroy", "vcm_map_error", "vcm_error_bounds")
 
 
 class VcmError(RuntimeError):
@@ -97,6 +98,27 @@ class vcm_batch_opts(ctypes.Structure):
                 ("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
+class vcm_server_opts(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+
+class vcm_request_info(ctypes.Structure):
+    _fields_ = [("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("viewpoints", ctypes.c_uint64)]
+
+
+class vcm_server_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("viewpoints", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("requests_per_s", ctypes.c_double), ("viewpoints_per_s", ctypes.c_double),
+                ("mem_in_use", ctypes.c_size_t), ("mem_peak", ctypes.c_size_t),
+                ("mem_budget", ctypes.c_size_t)]
+
+
 class vcm_batch_info(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("launches", ctypes.c_int32), ("graph", ctypes.c_int32),
@@ -144,9 +166,22 @@ def load_library(path: Optional[str] = None):
     L.vcm_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     L.vcm_batch_get_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_batch_info)]
     L.vcm_batch_destroy.argtypes = [ctypes.c_void_p]
+    L.vcm_server_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_server_opts),
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    L.vcm_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_query), ctypes.POINTER(vcm_result),
+                             ctypes.POINTER(ctypes.c_uint64)]
+    L.vcm_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(vcm_request_info)]
+    L.vcm_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
+                           ctypes.POINTER(vcm_request_info)]
+    L.vcm_server_drain.argtypes = [ctypes.c_void_p]
+    L.vcm_server_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_server_stats)]
+    L.vcm_server_reset_stats.argtypes = [ctypes.c_void_p]
+    L.vcm_server_destroy.argtypes = [ctypes.c_void_p]
     for name in ("vcm_build_index", "vcm_free_index", "vcm_index_get_info", "vcm_compute",
                  "vcm_compute_batch", "vcm_batch_create", "vcm_batch_run", "vcm_batch_get_info",
-                 "vcm_batch_destroy", "vcm_map_error", "vcm_error_bounds"):
+                 "vcm_batch_destroy", "vcm_server_create", "vcm_submit", "vcm_poll", "vcm_wait",
+                 "vcm_server_drain", "vcm_server_get_stats", "vcm_server_reset_stats",
+                 "vcm_server_destroy", "vcm_map_error", "vcm_error_bounds"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -343,6 +378,77 @@ class Batch:
         if self.handle:
             _check(load_library().vcm_batch_destroy(self.handle))
             self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A serving loop over one resident index (vcm_server_*).
+
+    submit() returns a ticket, or None when the memory budget is in use
+    (VCM_E_AGAIN: retry later); poll() returns None while the request runs,
+    else its info dict (raising VcmError if the request failed)."""
+
+    def __init__(self, index: Index, mem_budget_bytes: int = 0, max_inflight: int = 0,
+                 max_batch: int = 0, chunk: int = 0, blocks_per_cu: int = 0):
+        L = load_library()
+        opts = vcm_server_opts(int(mem_budget_bytes), int(max_inflight), int(max_batch), int(chunk),
+                               int(blocks_per_cu))
+        h = ctypes.c_void_p()
+        _check(L.vcm_server_create(index.handle, ctypes.byref(opts), ctypes.byref(h)))
+        self.handle = h
+        self._index = index
+        self._held = {}  # ticket -> result tensors, kept alive until finished
+
+    def submit(self, query: scenes.Query, result, precision: int = VCM_FP32_RECHECK):
+        Q = make_query(query, precision)
+        R = _make_result(query.grid.count, *result)
+        t = ctypes.c_uint64()
+        st = load_library().vcm_submit(self.handle, ctypes.byref(Q), ctypes.byref(R), ctypes.byref(t))
+        if st == VCM_E_AGAIN:
+            return None
+        _check(st)
+        self._held[t.value] = result
+        return t.value
+
+    def _finish(self, st, ticket, info):
+        if st == VCM_E_PENDING:
+            return None
+        self._held.pop(ticket, None)
+        _check(st)
+        return {"latency_ms": info.latency_ms, "queue_ms": info.queue_ms,
+                "viewpoints": info.viewpoints}
+
+    def poll(self, ticket: int):
+        info = vcm_request_info()
+        st = load_library().vcm_poll(self.handle, ticket, ctypes.byref(info))
+        return self._finish(st, ticket, info)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        info = vcm_request_info()
+        st = load_library().vcm_wait(self.handle, ticket, int(timeout_ms), ctypes.byref(info))
+        return self._finish(st, ticket, info)
+
+    def drain(self):
+        _check(load_library().vcm_server_drain(self.handle))
+
+    def stats(self):
+        s = vcm_server_stats()
+        _check(load_library().vcm_server_get_stats(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in vcm_server_stats._fields_}
+
+    def reset_stats(self):
+        _check(load_library().vcm_server_reset_stats(self.handle))
+
+    def close(self):
+        if self.handle:
+            _check(load_library().vcm_server_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+            self._held.clear()
 
     def __del__(self):
         try:

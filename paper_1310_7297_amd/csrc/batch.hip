@@ -176,7 +176,7 @@ void BatchPlan::layout() {
         g.end_off = off;
         off = align_up(off + sizeof(uint32_t) * g.members.size());
         g.ctr_off = off;
-        off = align_up(off + sizeof(unsigned) * kXcd);
+        off = align_up(off + kCounterBytes);
     }
     image_bytes = off;
     for (auto &pq : q) {

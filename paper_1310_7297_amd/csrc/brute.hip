@@ -456,23 +456,37 @@ __device__ inline unsigned range_begin(unsigned n, int r) {
     return static_cast<unsigned>((static_cast<unsigned long long>(n) * r) / kXcd);
 }
 
-__device__ inline bool next_item(unsigned *ctr, unsigned n_items, int &r, int &left,
-                                 unsigned &item) {
-    const int lane = threadIdx.x & 63;
-    while (left > 0) {
-        const unsigned b = range_begin(n_items, r), e = range_begin(n_items, r + 1);
-        unsigned i = 0;
-        if (lane == 0) i = atomicAdd(&ctr[r], 1u);
-        i = __builtin_amdgcn_readfirstlane(__shfl(i, 0));
-        if (i < e - b) {
-            item = b + i;
-            return true;
-        }
-        r = (r + 1) % kXcd;
-        --left;
+// Work-item dispenser of one wavefront.  (Issuing the next claim before
+// processing the current item, to hide the atomic's latency, measured slower:
+// the claim result stays live across the item and the loop's memory waits
+// cover it anyway.)
+struct Dispenser {
+    unsigned *ctr;
+    unsigned n;
+    int r, left;
+
+    __device__ void init(unsigned *c, unsigned n_items) {
+        ctr = c;
+        n = n_items;
+        r = blockIdx.x % kXcd;
+        left = kXcd;
     }
-    return false;
-}
+    __device__ bool next(unsigned &item) {
+        while (left > 0) {
+            unsigned i = 0;
+            if ((threadIdx.x & 63) == 0) i = atomicAdd(&ctr[r * kCtrStride], 1u);
+            i = __builtin_amdgcn_readfirstlane(__shfl(i, 0));
+            const unsigned b = range_begin(n, r), e = range_begin(n, r + 1);
+            if (i < e - b) {
+                item = b + i;
+                return true;
+            }
+            r = (r + 1) % kXcd;
+            --left;
+        }
+        return false;
+    }
+};
 
 // One work item of a query: A.chunk consecutive viewpoints of one grid row,
 // each traced by the whole wavefront; the results are written by A.chunk
@@ -595,9 +609,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     int *lds = lds_rays[wave];
     WaveStats ws;
     unsigned long long n_disagree = 0;
-    int r = blockIdx.x % kXcd, left = kXcd;
+    Dispenser D;
+    D.init(A.counter, A.n_items);
     unsigned item;
-    while (next_item(A.counter, A.n_items, r, left, item))
+    while (D.next(item))
         run_item<DIM, NS, EXACT64, MODE, STATS>(A, col_start, recs, item, lds, ws, n_disagree);
     flush_stats<STATS>(A.stats, ws, n_disagree);
 }
@@ -619,9 +634,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     int *lds = lds_rays[wave];
     WaveStats ws;
     unsigned long long n_disagree = 0;
-    int r = blockIdx.x % kXcd, left = kXcd;
+    Dispenser D;
+    D.init(B.counter, B.n_items);
     unsigned item;
-    while (next_item(B.counter, B.n_items, r, left, item)) {
+    while (D.next(item)) {
         int lo = 0, hi = B.nq - 1;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
@@ -639,7 +655,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 }
 
 __global__ void k_zero_counter(unsigned *c) {
-    if (threadIdx.x < kXcd) c[threadIdx.x] = 0u;
+    if (threadIdx.x < kXcd) c[threadIdx.x * kCtrStride] = 0u;
 }
 
 struct Launch {
@@ -775,7 +791,7 @@ vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_
     const int ns = slots_for(t);
     if (ns < 1 || ns > kMaxSlots) return set_error(VCM_E_INVALID, "too many target samples");
     unsigned *counter = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&counter), sizeof(unsigned) * kXcd, stream);
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&counter), kCounterBytes, stream);
     if (e != hipSuccess) return set_error(VCM_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     a.counter = counter;
     const GridDesc &g = a.grid;

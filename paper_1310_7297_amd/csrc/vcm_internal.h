@@ -23,6 +23,10 @@ constexpr int kMaxSlots = 6;
 
 // XCDs of an MI355X; work-item lists are split into this many ranges.
 constexpr int kXcd = 8;
+// The range counters sit 256 bytes apart, so that they do not share a cache
+// line (every claim is a device-scope atomic).
+constexpr int kCtrStride = 64;
+constexpr size_t kCounterBytes = sizeof(unsigned) * kXcd * kCtrStride;
 
 // One box reference inside a column list (32 bytes, one scalar load).
 // Coordinates are in the index frame (see DevIndex), where they are >= 0,
