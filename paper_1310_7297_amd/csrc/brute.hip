@@ -237,7 +237,7 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
         const int cy = static_cast<int>(floorf(q[1] * X.inv_cs));
         if (cx >= 0 && cx < X.nx && cy >= 0 && cy < X.ny) {
             const int col = cx + X.nx * cy;
-            const int rb = col_start[col], re = col_start[col + 1];
+            const int rb = col_start[col], re = col_start[col + 1] - 1;  // sentinel excluded
             for (int rr = rb; rr < re; ++rr) {
                 const BoxRec B = recs[rr];
                 if (DIM == 3 && B.hi[2] < q[2]) break;
@@ -255,15 +255,16 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     // ---- rays: slot j, lane l holds live sample j*64 + l
     float iv[NS][3];
     int sidx[NS];
-    bool zl[NS];  // the lane's ray has a zero direction component
     unsigned long long open[NS];
+    unsigned long long zmask[NS];  // rays with a zero direction component
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         sidx[j] = j * 64 + lane;
         const bool live = sidx[j] < N;
         float sp[3];
-        zl[j] = ray_setup<DIM>(T, faces, q, live ? sidx[j] : 0, sp, iv[j]);
+        const bool zl = ray_setup<DIM>(T, faces, q, live ? sidx[j] : 0, sp, iv[j]);
         open[j] = __ballot(live);
+        zmask[j] = __ballot(zl) & open[j];
     }
 
     // ---- corridor walk (wave-uniform), slabs prepared 64 at a time
@@ -282,14 +283,15 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     const float wz0 = F0[2] - qz, wz1 = F1[2] - qz;
     const float amin = fminf(qa, F0a), amax = fmaxf(qa, F1a);
     const float gend_a = na * X.cs, gend_b = nb * X.cs;
-    bool stop = !(amax >= 0.0f && amin < gend_a);
+    if (!(amax >= 0.0f && amin < gend_a)) goto walk_done;
+    {
     const int ia_lo = max(0, min(na - 1, (int)floorf(amin * X.inv_cs)));
     const int ia_hi = max(0, min(na - 1, (int)floorf(amax * X.inv_cs)));
     const int step = (qa <= ca) ? -1 : 1;
     const int ia_first = step < 0 ? ia_hi : ia_lo;
     const int n_slabs = ia_hi - ia_lo + 1;
 
-    for (int base = 0; !stop && base < n_slabs; base += 64) {
+    for (int base = 0; base < n_slabs; base += 64) {
         // lane l prepares slab base + l: the rectangles (1-l) q + l F meeting
         // the slab [A0, A1] along axis a give the corridor's extent [bl, bh]
         // along b and its lowest point zf there.
@@ -317,9 +319,9 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
         // the corridor's slice as an x-y rectangle, in ordered-integer form
         const unsigned ux0_l = ord(a == 0 ? A0 : bl), ux1_l = ord(a == 0 ? A1 : bh);
         const unsigned uy0_l = ord(a == 0 ? bl : A0), uy1_l = ord(a == 0 ? bh : A1);
-        const unsigned zf_l = ord(zf), zc_l = DIM == 3 ? ord(zc) : 0xffffffffu;
+        const unsigned zf_l = ord(zf), zc_l = DIM == 3 ? ord(zc) : 0x7f800000u;
         unsigned long long todo = __ballot(ok);
-        while (!stop && todo) {
+        while (todo) {
             const int sl = __builtin_ctzll(todo);
             todo &= todo - 1;
             const int ia = __builtin_amdgcn_readlane(ia_l, sl);
@@ -331,85 +333,91 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
             const unsigned uy1 = __builtin_amdgcn_readlane(uy1_l, sl);
             const unsigned uzf = __builtin_amdgcn_readlane(zf_l, sl);
             const unsigned uzc = __builtin_amdgcn_readlane(zc_l, sl);
-            for (int ib = ib0; !stop && ib <= ib1; ++ib) {
+            for (int ib = ib0; ib <= ib1; ++ib) {
                 const int col = a == 0 ? ia + X.nx * ib : ib + X.nx * ia;
-                const int rb = col_start[col], re = col_start[col + 1];
                 if (STATS) ++ws.cols;
-                for (int rr = rb; rr < re; ++rr) {
-                    const BoxRec B = recs[rr];
-                    // below the corridor's lowest point (so is the rest of the
-                    // list), or beside or above its slice: cannot meet its rays
-                    const bool low = DIM == 3 && __float_as_uint(B.hi[2]) < uzf;
-                    const bool beside =
-                        __float_as_uint(B.hi[0]) < ux0 || __float_as_uint(B.lo[0]) > ux1 ||
-                        __float_as_uint(B.hi[1]) < uy0 || __float_as_uint(B.lo[1]) > uy1 ||
-                        (DIM == 3 && __float_as_uint(B.lo[2]) > uzc);
-                    if (low || beside) {
-                        if (low) break;
-                        continue;
-                    }
-                    float blq[3], bhq[3];
+                // The list ends with a sentinel whose top is below every
+                // floor.  One loop exit, at the bottom: the scalar unit runs
+                // every record through the same few instructions.
+                const VCM_CONST BoxRec *rp = recs + col_start[col];
+                bool more;
+                do {
+                    const BoxRec B = *rp++;
+                    // Every coordinate of the index frame is a non-negative
+                    // float below 2^31 as an integer, so a signed difference
+                    // of two of them has the sign of their comparison.
+                    // Below the corridor's lowest point (so is the rest of
+                    // the list, and so is the sentinel): done with this
+                    // column.  (2-D boxes have an infinite top.)
+                    const bool low = static_cast<int>(__float_as_uint(B.hi[2]) - uzf) < 0;
+                    // Beside the slice, or above its ceiling: cannot meet its rays.
+                    const int side = static_cast<int>(__float_as_uint(B.hi[0]) - ux0) |
+                                     static_cast<int>(ux1 - __float_as_uint(B.lo[0])) |
+                                     static_cast<int>(__float_as_uint(B.hi[1]) - uy0) |
+                                     static_cast<int>(uy1 - __float_as_uint(B.lo[1])) |
+                                     (DIM == 3 ? static_cast<int>(uzc - __float_as_uint(B.lo[2])) : 0);
+                    more = !low;
+                    if (!low && side >= 0) {
+                        float blq[3], bhq[3];
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        blq[k] = B.lo[k] - q[k];
-                        bhq[k] = B.hi[k] - q[k];
-                    }
-                    unsigned long long hit_any = 0, open_any = 0;
-#pragma unroll
-                    for (int j = 0; j < NS; ++j) {
-                        if (!open[j]) continue;
-                        unsigned long long hit, unsure;
-                        float gap = 0.0f;
-                        if (EXACT64) {
-                            hit = 0;
-                            unsure = open[j];
-                        } else {
-                            // eps = +inf sends every test to the exact predicate
-                            gap = slab_gap<DIM>(iv[j], blq, bhq);
-                            hit = __ballot(gap > P.eps) & open[j];
-                            unsure = __ballot(fabsf(gap) <= P.eps || zl[j]) & open[j];
+                        for (int k = 0; k < 3; ++k) {
+                            blq[k] = B.lo[k] - q[k];
+                            bhq[k] = B.hi[k] - q[k];
                         }
-                        if (__builtin_expect(unsure != 0, 0)) {
-                            bool ex = false;
-                            if ((unsure >> lane) & 1) {
-                                float sp[3], d[3];
-                                // opaque copy: keeps this rare work out of the
-                                // hot loops (it is loop-invariant per ray)
-                                int si = sidx[j];
-                                asm volatile("" : "+v"(si));
-                                sample_pos<DIM>(T, faces, si, sp);
-                                float lq2[3], hq2[3];
+                        unsigned long long hit_any = 0, open_any = 0;
 #pragma unroll
-                                for (int k = 0; k < 3; ++k) {
-                                    d[k] = sp[k] - q[k];
-                                    // keep this rare path's work inside the branch
-                                    lq2[k] = blq[k];
-                                    hq2[k] = bhq[k];
-                                    asm volatile("" : "+v"(lq2[k]), "+v"(hq2[k]));
-                                }
-                                ex = exact_contact<DIM>(d, lq2, hq2);
-                                if (STATS && !EXACT64 && !zl[j] && fabsf(gap) > P.eps_ref &&
-                                    (gap > 0.0f) != ex)
-                                    ++n_disagree;
+                        for (int j = 0; j < NS; ++j) {
+                            if (!open[j]) continue;
+                            unsigned long long hit, unsure;
+                            float gap = 0.0f;
+                            if (EXACT64) {
+                                hit = 0;
+                                unsure = open[j];
+                            } else {
+                                // eps = +inf sends every test to the exact predicate
+                                gap = slab_gap<DIM>(iv[j], blq, bhq);
+                                hit = __ballot(gap > P.eps) & open[j];
+                                unsure = (__ballot(fabsf(gap) <= P.eps) | zmask[j]) & open[j];
                             }
-                            hit = (hit & ~unsure) | (__ballot(ex) & unsure);
+                            if (__builtin_expect(unsure != 0, 0)) {
+                                bool ex = false;
+                                if ((unsure >> lane) & 1) {
+                                    float sp[3], d[3];
+                                    // opaque copy: keeps this rare work out of
+                                    // the hot loops (it is loop-invariant per ray)
+                                    int si = sidx[j];
+                                    asm volatile("" : "+v"(si));
+                                    sample_pos<DIM>(T, faces, si, sp);
+                                    float lq2[3], hq2[3];
+#pragma unroll
+                                    for (int k = 0; k < 3; ++k) {
+                                        d[k] = sp[k] - q[k];
+                                        // keep this rare path's work inside the branch
+                                        lq2[k] = blq[k];
+                                        hq2[k] = bhq[k];
+                                        asm volatile("" : "+v"(lq2[k]), "+v"(hq2[k]));
+                                    }
+                                    ex = exact_contact<DIM>(d, lq2, hq2);
+                                    if (STATS && !EXACT64 && !((zmask[j] >> lane) & 1) &&
+                                        fabsf(gap) > P.eps_ref && (gap > 0.0f) != ex)
+                                        ++n_disagree;
+                                }
+                                hit = (hit & ~unsure) | (__ballot(ex) & unsure);
+                            }
+                            if (STATS) {
+                                ws.tests += __popcll(open[j]);
+                                ws.rechecks += EXACT64 ? 0 : __popcll(unsure);
+                                ++ws.slots;
+                            }
+                            open[j] &= ~hit;
+                            hit_any |= hit;
+                            open_any |= open[j];
                         }
-                        if (STATS) {
-                            ws.tests += __popcll(open[j]);
-                            ws.rechecks += EXACT64 ? 0 : __popcll(unsure);
-                            ++ws.slots;
-                        }
-                        open[j] &= ~hit;
-                        hit_any |= hit;
-                        open_any |= open[j];
+                        if (MODE == VCM_FULL ? hit_any != 0 : open_any == 0) goto walk_done;
                     }
-                    if (MODE == VCM_FULL ? hit_any != 0 : open_any == 0) {
-                        stop = true;
-                        break;
-                    }
-                }
+                } while (more);
                 // FRACTION mode: pack the unresolved rays into fewer slots
-                if (NS > 1 && MODE == VCM_FRACTION && !stop) {
+                if (NS > 1 && MODE == VCM_FRACTION) {
                     int tot = 0, used = 0;
 #pragma unroll
                     for (int j = 0; j < NS; ++j) {
@@ -431,8 +439,9 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
                             const bool live = j * 64 + lane < tot;
                             sidx[j] = live ? lds[j * 64 + lane] : 0;
                             float sp[3];
-                            zl[j] = ray_setup<DIM>(T, faces, q, sidx[j], sp, iv[j]);
+                            const bool zl = ray_setup<DIM>(T, faces, q, sidx[j], sp, iv[j]);
                             open[j] = __ballot(live);
+                            zmask[j] = __ballot(zl) & open[j];
                         }
                         __builtin_amdgcn_wave_barrier();
                     }
@@ -440,6 +449,8 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
             }
         }
     }
+    }
+walk_done:
     int vis = 0;
 #pragma unroll
     for (int j = 0; j < NS; ++j) vis += __popcll(open[j]);

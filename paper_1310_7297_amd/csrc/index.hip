@@ -43,7 +43,8 @@ __global__ void k_count(const float *__restrict__ lo, const float *__restrict__ 
         for (int32_t x = ax; x <= bx; ++x) atomicAdd(&counts[y * g.nx + x], 1);
 }
 
-// Exclusive scan of `n` counts into out[0..n] by one workgroup of 1024.
+// Exclusive scan of the list lengths (count + 1 for the sentinel that ends
+// every column) into out[0..n], by one workgroup of 1024.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ counts, int32_t n,
                                                int32_t *__restrict__ out) {
     __shared__ int32_t part[1024];
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ count
     const int32_t chunk = (n + 1023) / 1024;
     const int32_t b = min(n, t * chunk), e = min(n, b + chunk);
     int32_t s = 0;
-    for (int32_t i = b; i < e; ++i) s += counts[i];
+    for (int32_t i = b; i < e; ++i) s += counts[i] + 1;
     part[t] = s;
     __syncthreads();
     // Hillis-Steele inclusive scan of the 1024 partial sums.
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ count
     int32_t run = part[t] - s;
     for (int32_t i = b; i < e; ++i) {
         out[i] = run;
-        run += counts[i];
+        run += counts[i] + 1;
     }
     if (t == 1023) out[n] = part[1023];
 }
@@ -94,12 +95,24 @@ __global__ void k_fill(const float *__restrict__ lo, const float *__restrict__ h
 }
 
 // Sort each column list by (top height descending, box id ascending), which
-// also makes the index independent of the order the atomics handed out slots.
+// also makes the index independent of the order the atomics handed out slots,
+// and end it with the sentinel: a record whose top is -inf, bit pattern
+// 0xff800000, so that its difference with any floor of the traversal (an
+// ordered integer in [0, 0x7f800000]) is negative as a signed integer, and
+// whose lower corner is +inf.
 __global__ void k_sort(const int32_t *__restrict__ col_start, int32_t ncols,
                        BoxRec *__restrict__ recs) {
     int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncols) return;
-    const int32_t b = col_start[c], e = col_start[c + 1];
+    const int32_t b = col_start[c], e = col_start[c + 1] - 1;
+    BoxRec sen;
+    for (int k = 0; k < 3; ++k) {
+        sen.lo[k] = INFINITY;
+        sen.hi[k] = -INFINITY;
+    }
+    sen.id = -1;
+    sen.pad = 0;
+    recs[e] = sen;
     for (int32_t i = b + 1; i < e; ++i) {
         BoxRec key = recs[i];
         int32_t j = i - 1;
@@ -204,7 +217,7 @@ vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, i
     hipFree(d_cursor);
 
     ix->n_boxes = n;
-    ix->n_refs = total;
+    ix->n_refs = total - ncols;  // without the sentinels
     ix->dev.col_start = ix->d_col_start;
     ix->dev.recs = ix->d_recs;
     ix->frame[0] = x0;

@@ -44,6 +44,7 @@ struct alignas(32) BoxRec {
 struct DevIndex {
     const int32_t *col_start;  // nx*ny + 1 offsets into recs
     const BoxRec *recs;        // column lists, each sorted by decreasing hi.z
+                               // and ended by a sentinel record (top -inf)
     float x0, y0;              // grid origin in the frame (0, 0)
     float cs, inv_cs;          // cell size (a power of two) and its inverse
     int32_t nx, ny;
