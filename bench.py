@@ -24,6 +24,33 @@ OPS_PER_COLUMN = 12
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_HBM = 8.0e12
 
+# HBM bytes per launch of the timed kernel, from the committed rocprofv3
+# FETCH_SIZE / WRITE_SIZE summary (copy-kernel calibrated), valid only for the
+# kernel sources it was taken on.
+PROFILE = os.path.join(ROOT, "profiles", "k_brute_city20k_cube_fraction.md")
+TRAFFIC_BYTES = 125563838
+KERNEL_SOURCES = ("brute.hip", "index.hip", "vcm_internal.h")
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1310_7297_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(config: int, mode: str, cell: float):
+    """The profiled HBM bytes, or None if the workload or the kernel differs."""
+    if config != 3 or mode != "fraction" or cell not in (0.0, 32.0):
+        return None
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    return TRAFFIC_BYTES if kernel_sources_hash() in text else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -227,7 +254,8 @@ def main():
     ops = OPS_PER_BOX_TEST * st["box_tests"] + OPS_PER_COLUMN * st["columns"]
     achieved = ops / (kernel_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS,
+                "traffic": measured_traffic(args.config, args.mode, args.cell),
                 "kernel": "k_brute", "kernel_ms": kernel_ms,
                 "box_tests_per_launch": st["box_tests"], "columns_per_launch": st["columns"],
                 "rechecks_per_launch": st["rechecks"],
