@@ -29,6 +29,7 @@ PEAK_HBM = 8.0e12
 # kernel sources it was taken on.
 PROFILE = os.path.join(ROOT, "profiles", "k_brute_city20k_cube_fraction.md")
 TRAFFIC_BYTES = 125563838
+TRAFFIC_CELL = 32.0
 KERNEL_SOURCES = ("brute.hip", "index.hip", "vcm_internal.h")
 
 
@@ -43,7 +44,7 @@ def kernel_sources_hash() -> str:
 
 def measured_traffic(config: int, mode: str, cell: float):
     """The profiled HBM bytes, or None if the workload or the kernel differs."""
-    if config != 3 or mode != "fraction" or cell not in (0.0, 32.0):
+    if config != 3 or mode != "fraction" or cell != TRAFFIC_CELL:
         return None
     try:
         text = open(PROFILE).read()
@@ -59,7 +60,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=3, choices=(2, 3))
     ap.add_argument("--mode", default="fraction", choices=("fraction", "full"))
-    ap.add_argument("--cell", type=float, default=0.0)
+    ap.add_argument("--cell", type=float, default=-1.0,
+                    help="index column width; -1 (default): autotuned over 32/64/128 m for this "
+                         "workload; 0: the library's automatic width")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
@@ -234,8 +237,14 @@ def main():
     q.params.mode = mode
     n_vp = q.grid.count
 
+    tuning = None
+    cell = args.cell
+    if cell < 0:
+        # index autotuner (untimed set-up): fastest column width for this map
+        tuning = vcm.vcm_tune_cell_size(scene, [q], cell_min=32.0, cell_max=128.0, reps=1)
+        cell = tuning["best_cell"]
     t0 = time.perf_counter()
-    idx = vcm.vcm_build_index(scene, cell_size=args.cell)
+    idx = vcm.vcm_build_index(scene, cell_size=cell)
     info = idx.info()
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
@@ -255,7 +264,7 @@ def main():
     achieved = ops / (kernel_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS,
-                "traffic": measured_traffic(args.config, args.mode, args.cell),
+                "traffic": measured_traffic(args.config, args.mode, info["cell_size"]),
                 "kernel": "k_brute", "kernel_ms": kernel_ms,
                 "box_tests_per_launch": st["box_tests"], "columns_per_launch": st["columns"],
                 "rechecks_per_launch": st["rechecks"],
@@ -316,7 +325,8 @@ def main():
         "rays_per_s": rays_ps,
         "rays_per_step": st["rays"],
         "index": {"build_s": build_s, "device_bytes": info["device_bytes"], "refs": info["n_refs"],
-                  "columns": [info["nx"], info["ny"]]},
+                  "columns": [info["nx"], info["ny"]], "cell_size": info["cell_size"],
+                  "cell_tuning": tuning},
         "roofline": roofline,
         "cpu_baseline": cpu,
         **extra,

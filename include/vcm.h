@@ -99,6 +99,7 @@ typedef struct {
 vcm_status vcm_index_get_info(const vcm_index *index, vcm_index_info *info);
 
 /* --------------------------------------------------------------- queries --- */
+/* (vcm_tune_cell_size, which needs the query type, follows the batches.) */
 
 typedef enum {
     VCM_SEGMENT = 0,   /* 2-D line target (Sec. III uses it for exposition) */
@@ -253,6 +254,33 @@ vcm_status vcm_batch_run(vcm_batch *batch, void *stream);
 vcm_status vcm_batch_get_info(const vcm_batch *batch, vcm_batch_info *info);
 /* Wait for the device, then release the batch. */
 vcm_status vcm_batch_destroy(vcm_batch *batch);
+
+/* -------------------------------------------------------------- autotuning --- */
+
+/* The column width of the index is a trade-off: narrow columns list fewer
+ * boxes that a corridor only grazes, wide columns cost fewer column visits
+ * and list each box fewer times.  vcm_tune_cell_size builds the index of
+ * `obstacles` at every power of two from cell_min to cell_max, times the
+ * given queries on it (one warm-up and `reps` timed runs of the batch, the
+ * fastest kept), and returns the fastest width, for vcm_index_opts.cell_size.
+ * Blocking; allocates result buffers for the queries for the duration of the
+ * call. */
+typedef struct {
+    double cell_min;    /* smallest candidate width (power of two); 0 = 16   */
+    double cell_max;    /* largest; 0 = 128                                 */
+    int32_t device;
+    int32_t reps;       /* timed runs per width, 1..100; 0 = 2              */
+} vcm_tune_opts;
+
+typedef struct {
+    double best_cell;
+    int32_t n;          /* widths tried (at most 16)                         */
+    double cell[16];    /* widths the index used (a grid too fine is coarsened) */
+    double ms[16];      /* fastest time of the queries at that width         */
+} vcm_tune_result;
+
+vcm_status vcm_tune_cell_size(const vcm_obstacles *obstacles, const vcm_query *queries, int32_t nq,
+                              const vcm_tune_opts *opts, vcm_tune_result *out);
 
 /* ---------------------------------------------------------------- serving --- */
 

@@ -30,7 +30,8 @@ EXPORTS = ("vcm_last_error", "vcm_version", "vcm_build_index", "vcm_free_index",
            "vcm_index_get_info", "vcm_compute", "vcm_compute_batch", "vcm_batch_create",
            "vcm_batch_run", "vcm_batch_get_info", "vcm_batch_destroy", "vcm_server_create",
            "vcm_submit", "vcm_poll", "vcm_wait", "vcm_server_drain", "vcm_server_get_stats",
-           "vcm_server_reset_stats", "vcm_server_destroy", "vcm_map_error", "vcm_error_bounds")
+           "vcm_server_reset_stats", "vcm_server_destroy", "vcm_tune_cell_size", "vcm_map_error",
+           "vcm_error_bounds")
 
 
 class VcmError(RuntimeError):
@@ -96,6 +97,16 @@ class vcm_result(ctypes.Structure):
 class vcm_batch_opts(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class vcm_tune_opts(ctypes.Structure):
+    _fields_ = [("cell_min", ctypes.c_double), ("cell_max", ctypes.c_double),
+                ("device", ctypes.c_int32), ("reps", ctypes.c_int32)]
+
+
+class vcm_tune_result(ctypes.Structure):
+    _fields_ = [("best_cell", ctypes.c_double), ("n", ctypes.c_int32),
+                ("cell", ctypes.c_double * 16), ("ms", ctypes.c_double * 16)]
 
 
 class vcm_server_opts(ctypes.Structure):
@@ -177,11 +188,14 @@ def load_library(path: Optional[str] = None):
     L.vcm_server_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_server_stats)]
     L.vcm_server_reset_stats.argtypes = [ctypes.c_void_p]
     L.vcm_server_destroy.argtypes = [ctypes.c_void_p]
+    L.vcm_tune_cell_size.argtypes = [ctypes.POINTER(vcm_obstacles), ctypes.POINTER(vcm_query),
+                                     ctypes.c_int32, ctypes.POINTER(vcm_tune_opts),
+                                     ctypes.POINTER(vcm_tune_result)]
     for name in ("vcm_build_index", "vcm_free_index", "vcm_index_get_info", "vcm_compute",
                  "vcm_compute_batch", "vcm_batch_create", "vcm_batch_run", "vcm_batch_get_info",
                  "vcm_batch_destroy", "vcm_server_create", "vcm_submit", "vcm_poll", "vcm_wait",
                  "vcm_server_drain", "vcm_server_get_stats", "vcm_server_reset_stats",
-                 "vcm_server_destroy", "vcm_map_error", "vcm_error_bounds"):
+                 "vcm_server_destroy", "vcm_tune_cell_size", "vcm_map_error", "vcm_error_bounds"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -252,9 +266,8 @@ class Index:
             pass
 
 
-def vcm_build_index(scene: scenes.Scene, cell_size: float = 0.0, device: int = 0,
-                    stream: Optional[int] = None) -> Index:
-    L = load_library()
+def _obstacles(scene: scenes.Scene):
+    """vcm_obstacles over the scene's arrays (returned with them: keep alive)."""
     lo = np.ascontiguousarray(scene.lo, dtype=np.float64)
     hi = np.ascontiguousarray(scene.hi, dtype=np.float64)
     O = vcm_obstacles()
@@ -263,6 +276,13 @@ def vcm_build_index(scene: scenes.Scene, cell_size: float = 0.0, device: int = 0
     for k in range(3):
         O.lo[k] = lo[k].ctypes.data if O.n else None
         O.hi[k] = hi[k].ctypes.data if O.n else None
+    return O, (lo, hi)
+
+
+def vcm_build_index(scene: scenes.Scene, cell_size: float = 0.0, device: int = 0,
+                    stream: Optional[int] = None) -> Index:
+    L = load_library()
+    O, _keep = _obstacles(scene)
     opts = vcm_index_opts(float(cell_size), int(device), stream)
     h = ctypes.c_void_p()
     _check(L.vcm_build_index(ctypes.byref(O), ctypes.byref(opts), ctypes.byref(h)))
@@ -455,6 +475,23 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def vcm_tune_cell_size(scene: scenes.Scene, queries, cell_min: float = 0.0, cell_max: float = 0.0,
+                       reps: int = 0, device: int = 0, precision=VCM_FP32_RECHECK):
+    """Fastest index column width for these queries (vcm_tune_cell_size)."""
+    L = load_library()
+    O, _keep = _obstacles(scene)
+    if isinstance(precision, int):
+        precision = [precision] * len(queries)
+    Qs = (vcm_query * max(len(queries), 1))()
+    for i, q in enumerate(queries):
+        Qs[i] = make_query(q, precision[i])
+    opts = vcm_tune_opts(float(cell_min), float(cell_max), int(device), int(reps))
+    r = vcm_tune_result()
+    _check(L.vcm_tune_cell_size(ctypes.byref(O), Qs, len(queries), ctypes.byref(opts), ctypes.byref(r)))
+    return {"best_cell": r.best_cell, "cells": [r.cell[i] for i in range(r.n)],
+            "ms": [r.ms[i] for i in range(r.n)]}
 
 
 def vcm_map_error(c_exact, c_approx, stream=None):
