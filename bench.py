@@ -115,7 +115,8 @@ def bench_batch():
     import paper_1310_7297_amd as vcm
     from paper_1310_7297_amd import scenes
     scene, qs = scenes.config4()
-    idx = vcm.vcm_build_index(scene)
+    tuning = vcm.vcm_tune_cell_size(scene, qs[::8], cell_min=16.0, cell_max=64.0, reps=1)
+    idx = vcm.vcm_build_index(scene, cell_size=tuning["best_cell"])
     n_vp = sum(q.grid.count for q in qs)
     seq = [vcm.alloc_result(q.grid.count) for q in qs]
     res = [vcm.alloc_result(q.grid.count) for q in qs]
@@ -152,7 +153,7 @@ def bench_batch():
             "speedup_vs_sequential": t_seq / t_batch, "identical_to_sequential": bool(same),
             "chunk": info["chunk"], "blocks_per_cu": info["blocks_per_cu"],
             "launches": info["launches"], "graph": bool(info["graph"]),
-            "create_s": create_s, "autotune_ms": info["tune_ms"]}
+            "create_s": create_s, "autotune_ms": info["tune_ms"], "index_cell_tuning": tuning}
 
 
 def bench_serve(n_req: int):
@@ -164,7 +165,8 @@ def bench_serve(n_req: int):
     import paper_1310_7297_amd as vcm
     from paper_1310_7297_amd import scenes
     scene, qs = scenes.config5(n_requests=n_req)
-    idx = vcm.vcm_build_index(scene)
+    tuning = vcm.vcm_tune_cell_size(scene, qs[:32], cell_min=16.0, cell_max=64.0, reps=1)
+    idx = vcm.vcm_build_index(scene, cell_size=tuning["best_cell"])
     res = [vcm.alloc_result(q.grid.count) for q in qs]
     n_vp = sum(q.grid.count for q in qs)
     # sequential plain calls, back to back
@@ -179,7 +181,7 @@ def bench_serve(n_req: int):
     out = {"workload": "config5: 100,000-box 8 km city, Poisson arrivals, grids 64x64x16 / "
                        "128x128x32 / 256x256x64 (0.6/0.3/0.1)",
            "requests": n_req, "mean_viewpoints": n_vp / n_req,
-           "sequential_requests_per_s": n_req / t_seq, "rates": []}
+           "sequential_requests_per_s": n_req / t_seq, "index_cell_tuning": tuning, "rates": []}
     srv = vcm.Server(idx, max_inflight=2, max_batch=64)
     for rate in (100.0, 250.0, 500.0, 1000.0, 4000.0):
         srv.reset_stats()

@@ -130,6 +130,11 @@ __device__ inline int mbcnt(unsigned long long m) {
                                      __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(m), 0u));
 }
 
+// A wave-uniform float as a scalar-register value.
+__device__ inline float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
 // Position of sample `si` among the live samples of a viewpoint whose live
 // facets are `faces` (cube) or the single facet (segment, billboard).
 template <int DIM>
@@ -147,8 +152,12 @@ __device__ __attribute__((always_inline)) inline void sample_pos(const TargetDes
         const int fc = static_cast<int>((faces >> (4 * f)) & 7u);
         const int k = fc >> 1;
         const int ua = (k == 0) ? 1 : 0, vb = (k == 2) ? 1 : 2;
-        const float ck = k == 0 ? T.c[0] : (k == 1 ? T.c[1] : T.c[2]);
-        const float hk = k == 0 ? T.half[0] : (k == 1 ? T.half[1] : T.half[2]);
+        // k differs between lanes: select among scalar copies (values, not
+        // loads, so the selection does not become a per-lane memory load)
+        const float c0 = uniform_f(T.c[0]), c1 = uniform_f(T.c[1]), c2 = uniform_f(T.c[2]);
+        const float h0 = uniform_f(T.half[0]), h1 = uniform_f(T.half[1]), h2 = uniform_f(T.half[2]);
+        const float ck = k == 0 ? c0 : (k == 1 ? c1 : c2);
+        const float hk = k == 0 ? h0 : (k == 1 ? h1 : h2);
         const float plane = (fc & 1) ? ck + hk : ck - hk;
         s[0] = k == 0 ? plane : (ua == 0 ? T.c[0] + u : s[0]);
         s[1] = k == 1 ? plane : (ua == 1 ? T.c[1] + u : T.c[1] + v);
@@ -231,20 +240,28 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     const DevIndex &X = A.idx;
     const int lane = threadIdx.x & 63;
 
-    // ---- a viewpoint inside (or on) an obstacle sees nothing
-    {
+    // ---- a viewpoint inside (or on) an obstacle sees nothing.  Boxes of the
+    // index frame have no negative coordinate, so the scan of q's column
+    // compares ordered bit patterns on the scalar unit; the column's list
+    // ends with a sentinel (top -inf, lower corner +inf).
+    if (q[0] >= 0.0f && q[1] >= 0.0f && q[2] >= 0.0f) {
         const int cx = static_cast<int>(floorf(q[0] * X.inv_cs));
         const int cy = static_cast<int>(floorf(q[1] * X.inv_cs));
-        if (cx >= 0 && cx < X.nx && cy >= 0 && cy < X.ny) {
-            const int col = cx + X.nx * cy;
-            const int rb = col_start[col], re = col_start[col + 1] - 1;  // sentinel excluded
-            for (int rr = rb; rr < re; ++rr) {
-                const BoxRec B = recs[rr];
-                if (DIM == 3 && B.hi[2] < q[2]) break;
-                bool in = true;
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) in = in && B.lo[k] <= q[k] && q[k] <= B.hi[k];
-                if (in) {
+        if (cx < X.nx && cy < X.ny) {
+            const unsigned u0 = __builtin_amdgcn_readfirstlane(ord(q[0]));
+            const unsigned u1 = __builtin_amdgcn_readfirstlane(ord(q[1]));
+            const unsigned u2 = __builtin_amdgcn_readfirstlane(ord(q[2]));
+            const VCM_CONST BoxRec *rp = recs + col_start[cx + X.nx * cy];
+            for (;; ++rp) {
+                const BoxRec B = *rp;
+                // lower than q (so is the rest of the list, and the sentinel)
+                if (static_cast<int>(__float_as_uint(B.hi[2]) - u2) < 0) break;
+                const int out = static_cast<int>(u0 - __float_as_uint(B.lo[0])) |
+                                static_cast<int>(__float_as_uint(B.hi[0]) - u0) |
+                                static_cast<int>(u1 - __float_as_uint(B.lo[1])) |
+                                static_cast<int>(__float_as_uint(B.hi[1]) - u1) |
+                                (DIM == 3 ? static_cast<int>(u2 - __float_as_uint(B.lo[2])) : 0);
+                if (out >= 0) {
                     if (STATS) ++ws.inside;
                     return 0;
                 }
