@@ -135,12 +135,12 @@ __device__ inline float uniform_f(float x) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
-// Position of sample `si` among the live samples of a viewpoint whose live
-// facets are `faces` (cube) or the single facet (segment, billboard).
+// Position of local sample w (lattice index u fastest) of the facet with face
+// code fc (cube: 2k for the face at -k, 2k+1 for +k; other targets: their one
+// facet, fc ignored).
 template <int DIM>
-__device__ __attribute__((always_inline)) inline void sample_pos(const TargetDesc &T, unsigned faces, unsigned si, float *s) {
-    const unsigned f = static_cast<unsigned>((si * T.m_pf) >> 32);
-    const unsigned w = si - f * T.per_facet;
+__device__ __attribute__((always_inline)) inline void sample_pos_face(const TargetDesc &T, unsigned fc_u,
+                                                                      unsigned w, float *s) {
     const unsigned iv = static_cast<unsigned>((w * T.m_su) >> 32);
     const unsigned iu = w - iv * T.su;
     const float u = static_cast<float>(2 * static_cast<int>(iu) + 1 - T.su) * T.hu;
@@ -149,19 +149,19 @@ __device__ __attribute__((always_inline)) inline void sample_pos(const TargetDes
     s[1] = T.c[1];
     s[2] = DIM == 3 ? T.c[2] : 0.0f;
     if (T.kind == VCM_CUBE) {
-        const int fc = static_cast<int>((faces >> (4 * f)) & 7u);
+        const int fc = static_cast<int>(fc_u);
         const int k = fc >> 1;
-        const int ua = (k == 0) ? 1 : 0, vb = (k == 2) ? 1 : 2;
-        // k differs between lanes: select among scalar copies (values, not
+        const int ua = (k == 0) ? 1 : 0;
+        // k may differ between lanes: select among scalar copies (values, not
         // loads, so the selection does not become a per-lane memory load)
         const float c0 = uniform_f(T.c[0]), c1 = uniform_f(T.c[1]), c2 = uniform_f(T.c[2]);
         const float h0 = uniform_f(T.half[0]), h1 = uniform_f(T.half[1]), h2 = uniform_f(T.half[2]);
         const float ck = k == 0 ? c0 : (k == 1 ? c1 : c2);
         const float hk = k == 0 ? h0 : (k == 1 ? h1 : h2);
         const float plane = (fc & 1) ? ck + hk : ck - hk;
-        s[0] = k == 0 ? plane : (ua == 0 ? T.c[0] + u : s[0]);
-        s[1] = k == 1 ? plane : (ua == 1 ? T.c[1] + u : T.c[1] + v);
-        s[2] = k == 2 ? plane : T.c[2] + v;
+        s[0] = k == 0 ? plane : (ua == 0 ? c0 + u : s[0]);
+        s[1] = k == 1 ? plane : (ua == 1 ? c1 + u : c1 + v);
+        s[2] = k == 2 ? plane : c2 + v;
     } else {
         const int wax = 1 - T.nax;
         if (wax == 0) s[0] = T.c[0] + u;
@@ -170,13 +170,52 @@ __device__ __attribute__((always_inline)) inline void sample_pos(const TargetDes
     }
 }
 
+// Sample table of a launch: every sample of every facet (the cube's six faces
+// or the one facet), indexed by face code * per_facet + local index, in LDS.
+// A cube has at most 128 samples per face (three faces of live samples fit
+// the 384 ray slots), other targets at most 384: 768 entries.
+constexpr int kTableMax = 768;
+
+template <int DIM>
+__device__ void build_sample_table(const TargetDesc &T, float4 *tab) {
+    const int n = (T.kind == VCM_CUBE ? 6 : 1) * T.per_facet;
+    for (int t = threadIdx.x; t < n && t < kTableMax; t += blockDim.x) {
+        const unsigned fc = static_cast<unsigned>((static_cast<unsigned>(t) * T.m_pf) >> 32);
+        const unsigned w = static_cast<unsigned>(t) - fc * T.per_facet;
+        float sp[3];
+        sample_pos_face<DIM>(T, fc, w, sp);
+        tab[t] = make_float4(sp[0], sp[1], sp[2], 0.0f);
+    }
+    __syncthreads();
+}
+
+// Position of sample `si` among the live samples of a viewpoint whose live
+// facets are `faces` (cube, packed 4 bits per live face) or the single facet
+// (segment, billboard); from the sample table when one is given.
+template <int DIM, bool TAB>
+__device__ __attribute__((always_inline)) inline void sample_pos(const TargetDesc &T, unsigned faces, unsigned si,
+                                                                 float *s, const float4 *tab) {
+    const unsigned f = static_cast<unsigned>((si * T.m_pf) >> 32);
+    const unsigned w = si - f * T.per_facet;
+    const unsigned fc = T.kind == VCM_CUBE ? (faces >> (4 * f)) & 7u : 0u;
+    if (TAB) {
+        const float4 p = tab[fc * T.per_facet + w];
+        s[0] = p.x;
+        s[1] = p.y;
+        s[2] = p.z;
+    } else {
+        sample_pos_face<DIM>(T, fc, w, s);
+    }
+}
+
 // Rays of one slot: sample position and reciprocal direction per lane.  A
 // zero direction component gets reciprocal 0 and sends the lane's tests to
 // the exact predicate (zero_lane).
-template <int DIM>
+template <int DIM, bool TAB>
 __device__ __attribute__((always_inline)) inline bool ray_setup(const TargetDesc &T, unsigned faces, const float *q,
-                                 unsigned si, float *s, float *inv) {
-    sample_pos<DIM>(T, faces, si, s);
+                                                               unsigned si, float *s, float *inv,
+                                                               const float4 *tab) {
+    sample_pos<DIM, TAB>(T, faces, si, s, tab);
     bool zero = false;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -230,10 +269,10 @@ typedef const VCM_CONST BoxRec *cptr_rec;
 // corridor (top below its lowest point, or beside its extent along b) are
 // rejected by integer compares on the scalar unit, so only candidates cost
 // vector instructions.
-template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, bool TAB>
 __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     const BruteArgs &A, cptr_i32 col_start, cptr_rec recs, const float *q, unsigned faces,
-    int N, int *lds, WaveStats &ws,
+    int N, int *lds, const float4 *tab, WaveStats &ws,
     unsigned long long &n_disagree) {
     const TargetDesc &T = A.tgt;
     const ParamDesc &P = A.prm;
@@ -279,7 +318,7 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
         sidx[j] = j * 64 + lane;
         const bool live = sidx[j] < N;
         float sp[3];
-        const bool zl = ray_setup<DIM>(T, faces, q, live ? sidx[j] : 0, sp, iv[j]);
+        const bool zl = ray_setup<DIM, TAB>(T, faces, q, live ? sidx[j] : 0, sp, iv[j], tab);
         open[j] = __ballot(live);
         zmask[j] = __ballot(zl) & open[j];
     }
@@ -404,7 +443,7 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
                                     // the hot loops (it is loop-invariant per ray)
                                     int si = sidx[j];
                                     asm volatile("" : "+v"(si));
-                                    sample_pos<DIM>(T, faces, si, sp);
+                                    sample_pos<DIM, TAB>(T, faces, si, sp, tab);
                                     float lq2[3], hq2[3];
 #pragma unroll
                                     for (int k = 0; k < 3; ++k) {
@@ -456,7 +495,7 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
                             const bool live = j * 64 + lane < tot;
                             sidx[j] = live ? lds[j * 64 + lane] : 0;
                             float sp[3];
-                            const bool zl = ray_setup<DIM>(T, faces, q, sidx[j], sp, iv[j]);
+                            const bool zl = ray_setup<DIM, TAB>(T, faces, q, sidx[j], sp, iv[j], tab);
                             open[j] = __ballot(live);
                             zmask[j] = __ballot(zl) & open[j];
                         }
@@ -519,10 +558,10 @@ struct Dispenser {
 // One work item of a query: A.chunk consecutive viewpoints of one grid row,
 // each traced by the whole wavefront; the results are written by A.chunk
 // lanes at once.  `item` counts from the start of the query's items.
-template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, bool TAB>
 __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &A, cptr_i32 col_start,
                                                                cptr_rec recs, unsigned item, int *lds,
-                                                               WaveStats &ws,
+                                                               const float4 *tab, WaveStats &ws,
                                                                unsigned long long &n_disagree) {
     using R = typename std::conditional<EXACT64, double, float>::type;
     const int lane = threadIdx.x & 63;
@@ -576,8 +615,8 @@ __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &
         R col = R(0);
         if (fov && N > 0) {
             if (STATS) ws.rays += N;
-            const int vis = trace_viewpoint<DIM, NS, EXACT64, MODE, STATS>(A, col_start, recs, q, faces,
-                                                                            N, lds, ws, n_disagree);
+            const int vis = trace_viewpoint<DIM, NS, EXACT64, MODE, STATS, TAB>(
+                A, col_start, recs, q, faces, N, lds, tab, ws, n_disagree);
             if (MODE == VCM_FRACTION) {
                 cnt = vis;
                 if (vis > 0) col = (R(vis) / R(N)) * raw_colour<DIM, R>(T, P, q);
@@ -633,6 +672,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     const cptr_i32 col_start = (cptr_i32)col_start_g;
     const cptr_rec recs = (cptr_rec)recs_g;
     __shared__ int lds_rays[4][kMaxSamples];
+    __shared__ float4 s_tab[kTableMax];
+    build_sample_table<DIM>(A.tgt, s_tab);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int *lds = lds_rays[wave];
     WaveStats ws;
@@ -641,7 +682,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     D.init(A.counter, A.n_items);
     unsigned item;
     while (D.next(item))
-        run_item<DIM, NS, EXACT64, MODE, STATS>(A, col_start, recs, item, lds, ws, n_disagree);
+        run_item<DIM, NS, EXACT64, MODE, STATS, true>(A, col_start, recs, item, lds, s_tab, ws, n_disagree);
     flush_stats<STATS>(A.stats, ws, n_disagree);
 }
 
@@ -677,7 +718,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         // compiler turns the field reads back into scalar constant loads
         // (a local copy of the record would live in scratch memory)
         const BruteArgs &A = *reinterpret_cast<const BruteArgs *>(qs + lo);
-        run_item<DIM, NS, EXACT64, MODE, STATS>(A, col_start, recs, item - begin, lds, ws, n_disagree);
+        run_item<DIM, NS, EXACT64, MODE, STATS, false>(A, col_start, recs, item - begin, lds, nullptr, ws,
+                                                        n_disagree);
     }
     flush_stats<STATS>(B.stats, ws, n_disagree);
 }
