@@ -262,6 +262,75 @@ __device__ inline unsigned ord(float x) { return x > 0.0f ? __float_as_uint(x) :
 typedef const VCM_CONST int32_t *cptr_i32;
 typedef const VCM_CONST BoxRec *cptr_rec;
 
+// Test the open rays against one box B (slot by slot; a result within the
+// margin is settled by the exact predicate) and clear the rays it blocks.
+// Returns 0 when the viewpoint is decided (FULL mode: some ray is blocked;
+// FRACTION mode: no ray is left open), else a non-zero mask.
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, bool TAB>
+__device__ __attribute__((always_inline)) inline unsigned long long box_blocks(
+    const BoxRec &B, const TargetDesc &T, const ParamDesc &P, const float *q, unsigned faces,
+    const float4 *tab, const float (&iv)[NS][3], const int (&sidx)[NS], unsigned long long (&open)[NS],
+    const unsigned long long (&zmask)[NS], WaveStats &ws, unsigned long long &n_disagree) {
+    const int lane = threadIdx.x & 63;
+    float blq[3], bhq[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        blq[k] = B.lo[k] - q[k];
+        bhq[k] = B.hi[k] - q[k];
+    }
+    unsigned long long open_any = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        if (!open[j]) continue;
+        unsigned long long hit, unsure;
+        float gap = 0.0f;
+        if (EXACT64) {
+            hit = 0;
+            unsure = open[j];
+        } else {
+            // eps = +inf sends every test to the exact predicate
+            gap = slab_gap<DIM>(iv[j], blq, bhq);
+            hit = __ballot(gap > P.eps) & open[j];
+            unsure = (__ballot(fabsf(gap) <= P.eps) | zmask[j]) & open[j];
+        }
+        if (__builtin_expect(unsure != 0, 0)) {
+            bool ex = false;
+            if ((unsure >> lane) & 1) {
+                float sp[3], d[3];
+                // opaque copy: keeps this rare work out of the hot loops (it is
+                // loop-invariant per ray)
+                int si = sidx[j];
+                asm volatile("" : "+v"(si));
+                sample_pos<DIM, TAB>(T, faces, si, sp, tab);
+                float lq2[3], hq2[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    d[k] = sp[k] - q[k];
+                    // keep this rare path's work inside the branch
+                    lq2[k] = blq[k];
+                    hq2[k] = bhq[k];
+                    asm volatile("" : "+v"(lq2[k]), "+v"(hq2[k]));
+                }
+                ex = exact_contact<DIM>(d, lq2, hq2);
+                if (STATS && !EXACT64 && !((zmask[j] >> lane) & 1) && fabsf(gap) > P.eps_ref &&
+                    (gap > 0.0f) != ex)
+                    ++n_disagree;
+            }
+            hit = (hit & ~unsure) | (__ballot(ex) & unsure);
+        }
+        if (STATS) {
+            ws.tests += __popcll(open[j]);
+            ws.rechecks += EXACT64 ? 0 : __popcll(unsure);
+            ++ws.slots;
+        }
+        open[j] &= ~hit;
+        // FULL mode: one blocked ray decides the viewpoint
+        if (MODE == VCM_FULL && hit != 0) return 0;
+        open_any |= open[j];
+    }
+    return MODE == VCM_FULL ? ~0ull : open_any;
+}
+
 // Visibility of the live samples from q for one wavefront.  Returns the
 // number of unblocked live samples (FULL mode: exact only when it equals N).
 //
@@ -272,7 +341,7 @@ typedef const VCM_CONST BoxRec *cptr_rec;
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, bool TAB>
 __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     const BruteArgs &A, cptr_i32 col_start, cptr_rec recs, const float *q, unsigned faces,
-    int N, int *lds, const float4 *tab, WaveStats &ws,
+    int N, int *lds, const float4 *tab, int &blk, WaveStats &ws,
     unsigned long long &n_disagree) {
     const TargetDesc &T = A.tgt;
     const ParamDesc &P = A.prm;
@@ -321,6 +390,15 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
         const bool zl = ray_setup<DIM, TAB>(T, faces, q, live ? sidx[j] : 0, sp, iv[j], tab);
         open[j] = __ballot(live);
         zmask[j] = __ballot(zl) & open[j];
+    }
+
+    // ---- FULL mode: the box that blocked the previous viewpoint of this
+    // work item usually blocks this one too; one test settles it.
+    if (MODE == VCM_FULL && blk >= 0) {
+        const BoxRec B = recs[blk];
+        if (box_blocks<DIM, NS, EXACT64, MODE, STATS, TAB>(B, T, P, q, faces, tab, iv, sidx, open, zmask, ws,
+                                                           n_disagree) == 0)
+            return 0;
     }
 
     // ---- corridor walk (wave-uniform), slabs prepared 64 at a time
@@ -414,62 +492,12 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
                                      (DIM == 3 ? static_cast<int>(uzc - __float_as_uint(B.lo[2])) : 0);
                     more = !low;
                     if (!low && side >= 0) {
-                        float blq[3], bhq[3];
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            blq[k] = B.lo[k] - q[k];
-                            bhq[k] = B.hi[k] - q[k];
+                        const unsigned long long rest = box_blocks<DIM, NS, EXACT64, MODE, STATS, TAB>(
+                            B, T, P, q, faces, tab, iv, sidx, open, zmask, ws, n_disagree);
+                        if (rest == 0) {
+                            if (MODE == VCM_FULL) blk = static_cast<int>(rp - recs) - 1;
+                            goto walk_done;
                         }
-                        unsigned long long hit_any = 0, open_any = 0;
-#pragma unroll
-                        for (int j = 0; j < NS; ++j) {
-                            if (!open[j]) continue;
-                            unsigned long long hit, unsure;
-                            float gap = 0.0f;
-                            if (EXACT64) {
-                                hit = 0;
-                                unsure = open[j];
-                            } else {
-                                // eps = +inf sends every test to the exact predicate
-                                gap = slab_gap<DIM>(iv[j], blq, bhq);
-                                hit = __ballot(gap > P.eps) & open[j];
-                                unsure = (__ballot(fabsf(gap) <= P.eps) | zmask[j]) & open[j];
-                            }
-                            if (__builtin_expect(unsure != 0, 0)) {
-                                bool ex = false;
-                                if ((unsure >> lane) & 1) {
-                                    float sp[3], d[3];
-                                    // opaque copy: keeps this rare work out of
-                                    // the hot loops (it is loop-invariant per ray)
-                                    int si = sidx[j];
-                                    asm volatile("" : "+v"(si));
-                                    sample_pos<DIM, TAB>(T, faces, si, sp, tab);
-                                    float lq2[3], hq2[3];
-#pragma unroll
-                                    for (int k = 0; k < 3; ++k) {
-                                        d[k] = sp[k] - q[k];
-                                        // keep this rare path's work inside the branch
-                                        lq2[k] = blq[k];
-                                        hq2[k] = bhq[k];
-                                        asm volatile("" : "+v"(lq2[k]), "+v"(hq2[k]));
-                                    }
-                                    ex = exact_contact<DIM>(d, lq2, hq2);
-                                    if (STATS && !EXACT64 && !((zmask[j] >> lane) & 1) &&
-                                        fabsf(gap) > P.eps_ref && (gap > 0.0f) != ex)
-                                        ++n_disagree;
-                                }
-                                hit = (hit & ~unsure) | (__ballot(ex) & unsure);
-                            }
-                            if (STATS) {
-                                ws.tests += __popcll(open[j]);
-                                ws.rechecks += EXACT64 ? 0 : __popcll(unsure);
-                                ++ws.slots;
-                            }
-                            open[j] &= ~hit;
-                            hit_any |= hit;
-                            open_any |= open[j];
-                        }
-                        if (MODE == VCM_FULL ? hit_any != 0 : open_any == 0) goto walk_done;
                     }
                 } while (more);
                 // FRACTION mode: pack the unresolved rays into fewer slots
@@ -579,6 +607,7 @@ __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &
     float o_c = 0.0f;
     uint16_t o_cnt = 0;
     uint32_t o_gate = 0;
+    int blk = -1;  // record of the last blocking box (FULL mode)
     for (int t = 0; t < nv; ++t) {
         // grid index; in gate mode the launch grid is the block grid and
         // each block is represented by its lowest-index centre viewpoint
@@ -616,7 +645,7 @@ __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &
         if (fov && N > 0) {
             if (STATS) ws.rays += N;
             const int vis = trace_viewpoint<DIM, NS, EXACT64, MODE, STATS, TAB>(
-                A, col_start, recs, q, faces, N, lds, tab, ws, n_disagree);
+                A, col_start, recs, q, faces, N, lds, tab, blk, ws, n_disagree);
             if (MODE == VCM_FRACTION) {
                 cnt = vis;
                 if (vis > 0) col = (R(vis) / R(N)) * raw_colour<DIM, R>(T, P, q);
