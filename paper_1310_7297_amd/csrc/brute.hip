@@ -331,6 +331,151 @@ __device__ __attribute__((always_inline)) inline unsigned long long box_blocks(
     return MODE == VCM_FULL ? ~0ull : open_any;
 }
 
+// The corridor walk of one viewpoint (wave-uniform) along major axis AX:
+// the columns crossed by the convex hull of q and the target's box, slab by
+// slab from the target end, slabs prepared 64 at a time.  Clears the rays
+// the boxes met block; returns early when the viewpoint is decided.
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, bool TAB, int AX>
+__device__ __attribute__((always_inline)) inline void corridor_walk(
+    const BruteArgs &A, cptr_rec recs, cptr_i32 col_start, const float *q, unsigned faces, int *lds,
+    const float4 *tab, int &blk, float (&iv)[NS][3], int (&sidx)[NS], unsigned long long (&open)[NS],
+    unsigned long long (&zmask)[NS], WaveStats &ws, unsigned long long &n_disagree) {
+    const TargetDesc &T = A.tgt;
+    const ParamDesc &P = A.prm;
+    const DevIndex &X = A.idx;
+    const int lane = threadIdx.x & 63;
+    const float F0[3] = {T.c[0] - T.half[0], T.c[1] - T.half[1], T.c[2] - T.half[2]};
+    const float F1[3] = {T.c[0] + T.half[0], T.c[1] + T.half[1], T.c[2] + T.half[2]};
+    constexpr int BX = 1 - AX;  // the other horizontal axis
+    const int na = AX == 0 ? X.nx : X.ny, nb = AX == 0 ? X.ny : X.nx;
+    const float qa = q[AX], qb = q[BX], qz = q[2];
+    const float F0a = F0[AX], F1a = F1[AX];
+    const float F0b = F0[BX], F1b = F1[BX];
+    const float ca = T.c[AX];
+    const float ua0 = F0a - qa, ua1 = F1a - qa;
+    const float iua0 = ua0 != 0.0f ? __builtin_amdgcn_rcpf(ua0) : 0.0f;
+    const float iua1 = ua1 != 0.0f ? __builtin_amdgcn_rcpf(ua1) : 0.0f;
+    const float vb0 = F0b - qb, vb1 = F1b - qb;
+    const float wz0 = F0[2] - qz, wz1 = F1[2] - qz;
+    const float amin = fminf(qa, F0a), amax = fmaxf(qa, F1a);
+    const float gend_a = na * X.cs, gend_b = nb * X.cs;
+    if (!(amax >= 0.0f && amin < gend_a)) return;
+    {
+    const int ia_lo = max(0, min(na - 1, (int)floorf(amin * X.inv_cs)));
+    const int ia_hi = max(0, min(na - 1, (int)floorf(amax * X.inv_cs)));
+    const int step = (qa <= ca) ? -1 : 1;
+    const int ia_first = step < 0 ? ia_hi : ia_lo;
+    const int n_slabs = ia_hi - ia_lo + 1;
+
+    for (int base = 0; base < n_slabs; base += 64) {
+        // lane l prepares slab base + l: the rectangles (1-l) q + l F meeting
+        // the slab [A0, A1] along axis a give the corridor's extent [bl, bh]
+        // along b and its lowest point zf there.
+        const int ia_l = ia_first + step * (base + lane);
+        bool ok = base + lane < n_slabs;
+        const float A0 = ia_l * X.cs, A1 = A0 + X.cs;
+        float l0 = 0.0f, l1 = 1.0f;
+        const float r1 = A1 - qa, r2 = A0 - qa;
+        if (ua0 > 0.0f) l1 = fminf(l1, r1 * iua0);
+        else if (ua0 < 0.0f) l0 = fmaxf(l0, r1 * iua0);
+        else ok = ok && r1 >= 0.0f;
+        if (ua1 > 0.0f) l0 = fmaxf(l0, r2 * iua1);
+        else if (ua1 < 0.0f) l1 = fminf(l1, r2 * iua1);
+        else ok = ok && r2 <= 0.0f;
+        l0 = fmaxf(0.0f, l0 - kLambdaMargin);
+        l1 = fminf(1.0f, l1 + kLambdaMargin);
+        ok = ok && l0 <= l1;
+        const float bl = fminf(qb + l0 * vb0, qb + l1 * vb0) - kWalkMargin;
+        const float bh = fmaxf(qb + l0 * vb1, qb + l1 * vb1) + kWalkMargin;
+        ok = ok && bh >= 0.0f && bl < gend_b;
+        const float zf = DIM == 3 ? fminf(qz + l0 * wz0, qz + l1 * wz0) - kWalkMargin : 0.0f;
+        const float zc = DIM == 3 ? fmaxf(qz + l0 * wz1, qz + l1 * wz1) + kWalkMargin : 0.0f;
+        const int ib0_l = max(0, min(nb - 1, (int)floorf(bl * X.inv_cs)));
+        const int ib1_l = max(0, min(nb - 1, (int)floorf(bh * X.inv_cs)));
+        // the corridor's slice, in ordered-integer form: its extent along b
+        // (along a, every box listed in the slab's columns reaches the slab,
+        // up to the insertion margin) and its floor and ceiling
+        const unsigned ub0_l = ord(bl), ub1_l = ord(bh);
+        const unsigned zf_l = ord(zf), zc_l = DIM == 3 ? ord(zc) : 0x7f800000u;
+        const int ibp_l = ib0_l | (ib1_l << 16);
+        unsigned long long todo = __ballot(ok);
+        while (todo) {
+            const int sl = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int ia = ia_first + step * (base + sl);
+            const int ibp = __builtin_amdgcn_readlane(ibp_l, sl);
+            const int ib0 = ibp & 0xffff, ib1 = static_cast<int>(static_cast<unsigned>(ibp) >> 16);
+            const unsigned ub0 = __builtin_amdgcn_readlane(ub0_l, sl);
+            const unsigned ub1 = __builtin_amdgcn_readlane(ub1_l, sl);
+            const unsigned uzf = __builtin_amdgcn_readlane(zf_l, sl);
+            const unsigned uzc = __builtin_amdgcn_readlane(zc_l, sl);
+            for (int ib = ib0; ib <= ib1; ++ib) {
+                const int col = AX == 0 ? ia + X.nx * ib : ib + X.nx * ia;
+                if (STATS) ++ws.cols;
+                // The list ends with a sentinel whose top is below every
+                // floor.  One loop exit, at the bottom: the scalar unit runs
+                // every record through the same few instructions.
+                const VCM_CONST BoxRec *rp = recs + col_start[col];
+                bool more;
+                do {
+                    const BoxRec B = *rp++;
+                    // Every coordinate of the index frame is a non-negative
+                    // float below 2^31 as an integer, so a signed difference
+                    // of two of them has the sign of their comparison.
+                    // Below the corridor's lowest point (so is the rest of
+                    // the list, and so is the sentinel): done with this
+                    // column.  (2-D boxes have an infinite top.)
+                    const bool low = static_cast<int>(__float_as_uint(B.hi[2]) - uzf) < 0;
+                    // Beside the slice, or above its ceiling: cannot meet its rays.
+                    const int side = static_cast<int>(__float_as_uint(B.hi[BX]) - ub0) |
+                                     static_cast<int>(ub1 - __float_as_uint(B.lo[BX])) |
+                                     (DIM == 3 ? static_cast<int>(uzc - __float_as_uint(B.lo[2])) : 0);
+                    more = !low;
+                    if (!low && side >= 0) {
+                        const unsigned long long rest = box_blocks<DIM, NS, EXACT64, MODE, STATS, TAB>(
+                            B, T, P, q, faces, tab, iv, sidx, open, zmask, ws, n_disagree);
+                        if (rest == 0) {
+                            if (MODE == VCM_FULL) blk = static_cast<int>(rp - recs) - 1;
+                            return;
+                        }
+                    }
+                } while (more);
+                // FRACTION mode: pack the unresolved rays into fewer slots
+                if (NS > 1 && MODE == VCM_FRACTION) {
+                    int tot = 0, used = 0;
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) {
+                        tot += __popcll(open[j]);
+                        used += open[j] != 0;
+                    }
+                    if (((tot + 63) >> 6) < used) {
+                        int pos = 0;
+#pragma unroll
+                        for (int j = 0; j < NS; ++j) {
+                            if ((open[j] >> lane) & 1) lds[pos + mbcnt(open[j])] = sidx[j];
+                            pos += __popcll(open[j]);
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                        for (int j = 0; j < NS; ++j) {
+                            const bool live = j * 64 + lane < tot;
+                            sidx[j] = live ? lds[j * 64 + lane] : 0;
+                            float sp[3];
+                            const bool zl = ray_setup<DIM, TAB>(T, faces, q, sidx[j], sp, iv[j], tab);
+                            open[j] = __ballot(live);
+                            zmask[j] = __ballot(zl) & open[j];
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+            }
+        }
+    }
+    }
+}
+
 // Visibility of the live samples from q for one wavefront.  Returns the
 // number of unblocked live samples (FULL mode: exact only when it equals N).
 //
@@ -401,140 +546,13 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
             return 0;
     }
 
-    // ---- corridor walk (wave-uniform), slabs prepared 64 at a time
-    const float F0[3] = {T.c[0] - T.half[0], T.c[1] - T.half[1], T.c[2] - T.half[2]};
-    const float F1[3] = {T.c[0] + T.half[0], T.c[1] + T.half[1], T.c[2] + T.half[2]};
-    const int a = fabsf(T.c[0] - q[0]) >= fabsf(T.c[1] - q[1]) ? 0 : 1;
-    const int na = a == 0 ? X.nx : X.ny, nb = a == 0 ? X.ny : X.nx;
-    const float qa = a == 0 ? q[0] : q[1], qb = a == 0 ? q[1] : q[0], qz = q[2];
-    const float F0a = a == 0 ? F0[0] : F0[1], F1a = a == 0 ? F1[0] : F1[1];
-    const float F0b = a == 0 ? F0[1] : F0[0], F1b = a == 0 ? F1[1] : F1[0];
-    const float ca = a == 0 ? T.c[0] : T.c[1];
-    const float ua0 = F0a - qa, ua1 = F1a - qa;
-    const float iua0 = ua0 != 0.0f ? __builtin_amdgcn_rcpf(ua0) : 0.0f;
-    const float iua1 = ua1 != 0.0f ? __builtin_amdgcn_rcpf(ua1) : 0.0f;
-    const float vb0 = F0b - qb, vb1 = F1b - qb;
-    const float wz0 = F0[2] - qz, wz1 = F1[2] - qz;
-    const float amin = fminf(qa, F0a), amax = fmaxf(qa, F1a);
-    const float gend_a = na * X.cs, gend_b = nb * X.cs;
-    if (!(amax >= 0.0f && amin < gend_a)) goto walk_done;
-    {
-    const int ia_lo = max(0, min(na - 1, (int)floorf(amin * X.inv_cs)));
-    const int ia_hi = max(0, min(na - 1, (int)floorf(amax * X.inv_cs)));
-    const int step = (qa <= ca) ? -1 : 1;
-    const int ia_first = step < 0 ? ia_hi : ia_lo;
-    const int n_slabs = ia_hi - ia_lo + 1;
-
-    for (int base = 0; base < n_slabs; base += 64) {
-        // lane l prepares slab base + l: the rectangles (1-l) q + l F meeting
-        // the slab [A0, A1] along axis a give the corridor's extent [bl, bh]
-        // along b and its lowest point zf there.
-        const int ia_l = ia_first + step * (base + lane);
-        bool ok = base + lane < n_slabs;
-        const float A0 = ia_l * X.cs, A1 = A0 + X.cs;
-        float l0 = 0.0f, l1 = 1.0f;
-        const float r1 = A1 - qa, r2 = A0 - qa;
-        if (ua0 > 0.0f) l1 = fminf(l1, r1 * iua0);
-        else if (ua0 < 0.0f) l0 = fmaxf(l0, r1 * iua0);
-        else ok = ok && r1 >= 0.0f;
-        if (ua1 > 0.0f) l0 = fmaxf(l0, r2 * iua1);
-        else if (ua1 < 0.0f) l1 = fminf(l1, r2 * iua1);
-        else ok = ok && r2 <= 0.0f;
-        l0 = fmaxf(0.0f, l0 - kLambdaMargin);
-        l1 = fminf(1.0f, l1 + kLambdaMargin);
-        ok = ok && l0 <= l1;
-        const float bl = fminf(qb + l0 * vb0, qb + l1 * vb0) - kWalkMargin;
-        const float bh = fmaxf(qb + l0 * vb1, qb + l1 * vb1) + kWalkMargin;
-        ok = ok && bh >= 0.0f && bl < gend_b;
-        const float zf = DIM == 3 ? fminf(qz + l0 * wz0, qz + l1 * wz0) - kWalkMargin : 0.0f;
-        const float zc = DIM == 3 ? fmaxf(qz + l0 * wz1, qz + l1 * wz1) + kWalkMargin : 0.0f;
-        const int ib0_l = max(0, min(nb - 1, (int)floorf(bl * X.inv_cs)));
-        const int ib1_l = max(0, min(nb - 1, (int)floorf(bh * X.inv_cs)));
-        // the corridor's slice as an x-y rectangle, in ordered-integer form
-        const unsigned ux0_l = ord(a == 0 ? A0 : bl), ux1_l = ord(a == 0 ? A1 : bh);
-        const unsigned uy0_l = ord(a == 0 ? bl : A0), uy1_l = ord(a == 0 ? bh : A1);
-        const unsigned zf_l = ord(zf), zc_l = DIM == 3 ? ord(zc) : 0x7f800000u;
-        unsigned long long todo = __ballot(ok);
-        while (todo) {
-            const int sl = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const int ia = __builtin_amdgcn_readlane(ia_l, sl);
-            const int ib0 = __builtin_amdgcn_readlane(ib0_l, sl);
-            const int ib1 = __builtin_amdgcn_readlane(ib1_l, sl);
-            const unsigned ux0 = __builtin_amdgcn_readlane(ux0_l, sl);
-            const unsigned ux1 = __builtin_amdgcn_readlane(ux1_l, sl);
-            const unsigned uy0 = __builtin_amdgcn_readlane(uy0_l, sl);
-            const unsigned uy1 = __builtin_amdgcn_readlane(uy1_l, sl);
-            const unsigned uzf = __builtin_amdgcn_readlane(zf_l, sl);
-            const unsigned uzc = __builtin_amdgcn_readlane(zc_l, sl);
-            for (int ib = ib0; ib <= ib1; ++ib) {
-                const int col = a == 0 ? ia + X.nx * ib : ib + X.nx * ia;
-                if (STATS) ++ws.cols;
-                // The list ends with a sentinel whose top is below every
-                // floor.  One loop exit, at the bottom: the scalar unit runs
-                // every record through the same few instructions.
-                const VCM_CONST BoxRec *rp = recs + col_start[col];
-                bool more;
-                do {
-                    const BoxRec B = *rp++;
-                    // Every coordinate of the index frame is a non-negative
-                    // float below 2^31 as an integer, so a signed difference
-                    // of two of them has the sign of their comparison.
-                    // Below the corridor's lowest point (so is the rest of
-                    // the list, and so is the sentinel): done with this
-                    // column.  (2-D boxes have an infinite top.)
-                    const bool low = static_cast<int>(__float_as_uint(B.hi[2]) - uzf) < 0;
-                    // Beside the slice, or above its ceiling: cannot meet its rays.
-                    const int side = static_cast<int>(__float_as_uint(B.hi[0]) - ux0) |
-                                     static_cast<int>(ux1 - __float_as_uint(B.lo[0])) |
-                                     static_cast<int>(__float_as_uint(B.hi[1]) - uy0) |
-                                     static_cast<int>(uy1 - __float_as_uint(B.lo[1])) |
-                                     (DIM == 3 ? static_cast<int>(uzc - __float_as_uint(B.lo[2])) : 0);
-                    more = !low;
-                    if (!low && side >= 0) {
-                        const unsigned long long rest = box_blocks<DIM, NS, EXACT64, MODE, STATS, TAB>(
-                            B, T, P, q, faces, tab, iv, sidx, open, zmask, ws, n_disagree);
-                        if (rest == 0) {
-                            if (MODE == VCM_FULL) blk = static_cast<int>(rp - recs) - 1;
-                            goto walk_done;
-                        }
-                    }
-                } while (more);
-                // FRACTION mode: pack the unresolved rays into fewer slots
-                if (NS > 1 && MODE == VCM_FRACTION) {
-                    int tot = 0, used = 0;
-#pragma unroll
-                    for (int j = 0; j < NS; ++j) {
-                        tot += __popcll(open[j]);
-                        used += open[j] != 0;
-                    }
-                    if (((tot + 63) >> 6) < used) {
-                        int pos = 0;
-#pragma unroll
-                        for (int j = 0; j < NS; ++j) {
-                            if ((open[j] >> lane) & 1) lds[pos + mbcnt(open[j])] = sidx[j];
-                            pos += __popcll(open[j]);
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-                        for (int j = 0; j < NS; ++j) {
-                            const bool live = j * 64 + lane < tot;
-                            sidx[j] = live ? lds[j * 64 + lane] : 0;
-                            float sp[3];
-                            const bool zl = ray_setup<DIM, TAB>(T, faces, q, sidx[j], sp, iv[j], tab);
-                            open[j] = __ballot(live);
-                            zmask[j] = __ballot(zl) & open[j];
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                    }
-                }
-            }
-        }
-    }
-    }
-walk_done:
+    // ---- corridor walk along the major horizontal axis of q - c
+    if (fabsf(T.c[0] - q[0]) >= fabsf(T.c[1] - q[1]))
+        corridor_walk<DIM, NS, EXACT64, MODE, STATS, TAB, 0>(A, recs, col_start, q, faces, lds, tab, blk, iv,
+                                                             sidx, open, zmask, ws, n_disagree);
+    else
+        corridor_walk<DIM, NS, EXACT64, MODE, STATS, TAB, 1>(A, recs, col_start, q, faces, lds, tab, blk, iv,
+                                                             sidx, open, zmask, ws, n_disagree);
     int vis = 0;
 #pragma unroll
     for (int j = 0; j < NS; ++j) vis += __popcll(open[j]);

@@ -167,7 +167,9 @@ vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, i
     double y0 = std::floor((mny - kFatMargin) / cs) * cs;
     int64_t nx = (int64_t)std::floor((mxx + kFatMargin - x0) / cs) + 1;
     int64_t ny = (int64_t)std::floor((mxy + kFatMargin - y0) / cs) + 1;
-    while (nx * ny > (int64_t(1) << 24)) {
+    // at most 2^24 columns, and at most 65535 along each axis (the traversal
+    // packs two column indices into one 32-bit word)
+    while (nx * ny > (int64_t(1) << 24) || nx > 65535 || ny > 65535) {
         cs *= 2;
         x0 = std::floor((mnx - kFatMargin) / cs) * cs;
         y0 = std::floor((mny - kFatMargin) / cs) * cs;
