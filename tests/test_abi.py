@@ -82,3 +82,15 @@ def test_error_bounds_match_oracle(cfg, dim):
     assert got["tangent"] == pytest.approx(want["tangent"], rel=1e-12)
     with pytest.raises(vcm.VcmError):
         vcm.vcm_error_bounds(q, 4)
+
+
+def test_tune_cell_size_rejects_bad_widths():
+    """Argument checks of the index autotuner precede any device work."""
+    scene, q = scenes.config1()
+    for kw in ({"cell_min": 24.0}, {"cell_min": 64.0, "cell_max": 32.0}, {"cell_max": 8192.0},
+               {"reps": 101}):
+        with pytest.raises(vcm.VcmError) as e:
+            vcm.vcm_tune_cell_size(scene, [q], **kw)
+        assert e.value.status == vcm.VCM_E_INVALID
+    with pytest.raises(vcm.VcmError):
+        vcm.vcm_tune_cell_size(scene, [], cell_min=16.0)
