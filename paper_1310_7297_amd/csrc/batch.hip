@@ -166,6 +166,7 @@ void BatchPlan::layout() {
         }
         g->members.push_back(static_cast<int>(i));
         g->ns = std::max(g->ns, pq.ns);
+        for (int k = 0; k < 3; ++k) g->packed_table = g->packed_table && pq.t.half[k] < 4096.0f;
         g->n_items += static_cast<uint32_t>(it);
         items += it;
     }
@@ -212,7 +213,7 @@ vcm_status BatchPlan::enqueue(hipStream_t s, DevStats *stats) const {
         b.nq = static_cast<int32_t>(g.members.size());
         b.n_items = g.n_items;
         const int64_t blocks = std::min<int64_t>((int64_t(g.n_items) + 3) / 4, int64_t(cus) * tune.blocks_per_cu);
-        vcm_status st = launch_brute_batch(*ix, g.fp64, g.mode, g.ns, b,
+        vcm_status st = launch_brute_batch(*ix, g.fp64, g.mode, g.ns, g.packed_table, b,
                                            reinterpret_cast<const BruteArgs *>(d_base + g.rec_off),
                                            reinterpret_cast<const uint32_t *>(d_base + g.end_off),
                                            static_cast<int>(std::max<int64_t>(blocks, 1)), s);

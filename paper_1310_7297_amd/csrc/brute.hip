@@ -189,20 +189,59 @@ __device__ void build_sample_table(const TargetDesc &T, float4 *tab) {
     __syncthreads();
 }
 
+// Sample sources: lattice arithmetic, the workgroup's float table, or a
+// wavefront's packed table (batched launches, whose wavefronts may serve
+// different queries).
+constexpr int kTabNone = 0, kTabBlock = 1, kTabWave = 2;
+
+// Packed table of one wavefront: per sample, its offsets from the target
+// centre in units of 2^-8 m as three signed 21-bit fields of 64 bits (exact
+// for targets of half-extent below 4096 m, which the host checks).  Written
+// and read by the same wavefront.
+template <int DIM>
+__device__ void build_wave_table(const TargetDesc &T, uint2 *tab) {
+    const int lane = threadIdx.x & 63;
+    const int n = (T.kind == VCM_CUBE ? 6 : 1) * T.per_facet;
+    for (int t = lane; t < n && t < kTableMax; t += 64) {
+        const unsigned fc = static_cast<unsigned>((static_cast<unsigned>(t) * T.m_pf) >> 32);
+        const unsigned w = static_cast<unsigned>(t) - fc * T.per_facet;
+        float sp[3];
+        sample_pos_face<DIM>(T, fc, w, sp);
+        const long long ox = static_cast<int>((sp[0] - T.c[0]) * 256.0f) & 0x1fffff;
+        const long long oy = static_cast<int>((sp[1] - T.c[1]) * 256.0f) & 0x1fffff;
+        const long long oz = DIM == 3 ? static_cast<int>((sp[2] - T.c[2]) * 256.0f) & 0x1fffff : 0;
+        const long long v = ox | (oy << 21) | (oz << 42);
+        tab[t] = make_uint2(static_cast<unsigned>(v), static_cast<unsigned>(v >> 32));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Position of sample `si` among the live samples of a viewpoint whose live
 // facets are `faces` (cube, packed 4 bits per live face) or the single facet
 // (segment, billboard); from the sample table when one is given.
-template <int DIM, bool TAB>
+template <int DIM, int TAB>
 __device__ __attribute__((always_inline)) inline void sample_pos(const TargetDesc &T, unsigned faces, unsigned si,
-                                                                 float *s, const float4 *tab) {
+                                                                 float *s, const void *tab) {
     const unsigned f = static_cast<unsigned>((si * T.m_pf) >> 32);
     const unsigned w = si - f * T.per_facet;
     const unsigned fc = T.kind == VCM_CUBE ? (faces >> (4 * f)) & 7u : 0u;
-    if (TAB) {
-        const float4 p = tab[fc * T.per_facet + w];
+    if (TAB == kTabBlock) {
+        const float4 p = static_cast<const float4 *>(tab)[fc * T.per_facet + w];
         s[0] = p.x;
         s[1] = p.y;
         s[2] = p.z;
+    } else if (TAB == kTabWave) {
+        // three signed 21-bit offsets from the target centre, in 2^-8 m
+        const uint2 e = static_cast<const uint2 *>(tab)[fc * T.per_facet + w];
+        const long long v = static_cast<long long>(e.x) | (static_cast<long long>(e.y) << 32);
+        const int ox = static_cast<int>((v << 43) >> 43);
+        const int oy = static_cast<int>((v << 22) >> 43);
+        const int oz = static_cast<int>((v << 1) >> 43);
+        s[0] = T.c[0] + static_cast<float>(ox) * 0x1p-8f;
+        s[1] = T.c[1] + static_cast<float>(oy) * 0x1p-8f;
+        s[2] = DIM == 3 ? T.c[2] + static_cast<float>(oz) * 0x1p-8f : 0.0f;
     } else {
         sample_pos_face<DIM>(T, fc, w, s);
     }
@@ -211,10 +250,10 @@ __device__ __attribute__((always_inline)) inline void sample_pos(const TargetDes
 // Rays of one slot: sample position and reciprocal direction per lane.  A
 // zero direction component gets reciprocal 0 and sends the lane's tests to
 // the exact predicate (zero_lane).
-template <int DIM, bool TAB>
+template <int DIM, int TAB>
 __device__ __attribute__((always_inline)) inline bool ray_setup(const TargetDesc &T, unsigned faces, const float *q,
                                                                unsigned si, float *s, float *inv,
-                                                               const float4 *tab) {
+                                                               const void *tab) {
     sample_pos<DIM, TAB>(T, faces, si, s, tab);
     bool zero = false;
 #pragma unroll
@@ -266,10 +305,10 @@ typedef const VCM_CONST BoxRec *cptr_rec;
 // margin is settled by the exact predicate) and clear the rays it blocks.
 // Returns 0 when the viewpoint is decided (FULL mode: some ray is blocked;
 // FRACTION mode: no ray is left open), else a non-zero mask.
-template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, bool TAB>
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
 __device__ __attribute__((always_inline)) inline unsigned long long box_blocks(
     const BoxRec &B, const TargetDesc &T, const ParamDesc &P, const float *q, unsigned faces,
-    const float4 *tab, const float (&iv)[NS][3], const int (&sidx)[NS], unsigned long long (&open)[NS],
+    const void *tab, const float (&iv)[NS][3], const int (&sidx)[NS], unsigned long long (&open)[NS],
     const unsigned long long (&zmask)[NS], WaveStats &ws, unsigned long long &n_disagree) {
     const int lane = threadIdx.x & 63;
     float blq[3], bhq[3];
@@ -335,10 +374,10 @@ __device__ __attribute__((always_inline)) inline unsigned long long box_blocks(
 // the columns crossed by the convex hull of q and the target's box, slab by
 // slab from the target end, slabs prepared 64 at a time.  Clears the rays
 // the boxes met block; returns early when the viewpoint is decided.
-template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, bool TAB, int AX>
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB, int AX>
 __device__ __attribute__((always_inline)) inline void corridor_walk(
     const BruteArgs &A, cptr_rec recs, cptr_i32 col_start, const float *q, unsigned faces, int *lds,
-    const float4 *tab, int &blk, float (&iv)[NS][3], int (&sidx)[NS], unsigned long long (&open)[NS],
+    const void *tab, int &blk, float (&iv)[NS][3], int (&sidx)[NS], unsigned long long (&open)[NS],
     unsigned long long (&zmask)[NS], WaveStats &ws, unsigned long long &n_disagree) {
     const TargetDesc &T = A.tgt;
     const ParamDesc &P = A.prm;
@@ -483,10 +522,10 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
 // corridor (top below its lowest point, or beside its extent along b) are
 // rejected by integer compares on the scalar unit, so only candidates cost
 // vector instructions.
-template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, bool TAB>
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
 __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     const BruteArgs &A, cptr_i32 col_start, cptr_rec recs, const float *q, unsigned faces,
-    int N, int *lds, const float4 *tab, int &blk, WaveStats &ws,
+    int N, int *lds, const void *tab, int &blk, WaveStats &ws,
     unsigned long long &n_disagree) {
     const TargetDesc &T = A.tgt;
     const ParamDesc &P = A.prm;
@@ -604,10 +643,10 @@ struct Dispenser {
 // One work item of a query: A.chunk consecutive viewpoints of one grid row,
 // each traced by the whole wavefront; the results are written by A.chunk
 // lanes at once.  `item` counts from the start of the query's items.
-template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, bool TAB>
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
 __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &A, cptr_i32 col_start,
                                                                cptr_rec recs, unsigned item, int *lds,
-                                                               const float4 *tab, WaveStats &ws,
+                                                               const void *tab, WaveStats &ws,
                                                                unsigned long long &n_disagree) {
     using R = typename std::conditional<EXACT64, double, float>::type;
     const int lane = threadIdx.x & 63;
@@ -729,7 +768,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     D.init(A.counter, A.n_items);
     unsigned item;
     while (D.next(item))
-        run_item<DIM, NS, EXACT64, MODE, STATS, true>(A, col_start, recs, item, lds, s_tab, ws, n_disagree);
+        run_item<DIM, NS, EXACT64, MODE, STATS, kTabBlock>(A, col_start, recs, item, lds, s_tab, ws, n_disagree);
     flush_stats<STATS>(A.stats, ws, n_disagree);
 }
 
@@ -737,7 +776,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 // form one list (query after query); a wavefront finds the query of an item
 // by binary search over the queries' item ends and reads the query's record
 // from constant memory (scalar loads).
-template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_brute_batch(
     BatchArgs B, const BruteArgs *qs_g, const uint32_t *item_end_g, const int32_t *col_start_g,
     const BoxRec *recs_g) {
@@ -746,8 +785,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     const VCM_CONST BruteArgs *qs = (const VCM_CONST BruteArgs *)qs_g;
     const VCM_CONST uint32_t *item_end = (const VCM_CONST uint32_t *)item_end_g;
     __shared__ int lds_rays[4][kMaxSamples];
+    __shared__ uint2 s_wtab[TAB == kTabWave ? 4 : 1][TAB == kTabWave ? kTableMax : 1];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int *lds = lds_rays[wave];
+    uint2 *wtab = s_wtab[TAB == kTabWave ? wave : 0];
+    int cur_q = -1;  // query whose samples the wavefront's table holds
     WaveStats ws;
     unsigned long long n_disagree = 0;
     Dispenser D;
@@ -765,8 +807,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         // compiler turns the field reads back into scalar constant loads
         // (a local copy of the record would live in scratch memory)
         const BruteArgs &A = *reinterpret_cast<const BruteArgs *>(qs + lo);
-        run_item<DIM, NS, EXACT64, MODE, STATS, false>(A, col_start, recs, item - begin, lds, nullptr, ws,
-                                                        n_disagree);
+        if (TAB == kTabWave && lo != cur_q) {
+            build_wave_table<DIM>(A.tgt, wtab);
+            cur_q = lo;
+        }
+        run_item<DIM, NS, EXACT64, MODE, STATS, TAB>(A, col_start, recs, item - begin, lds, wtab, ws,
+                                                      n_disagree);
     }
     flush_stats<STATS>(B.stats, ws, n_disagree);
 }
@@ -883,16 +929,20 @@ void launch_zero_counter(unsigned *c, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, c);
 }
 
-vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, const BatchArgs &b,
-                              const BruteArgs *d_recs, const uint32_t *d_item_end, int blocks,
-                              hipStream_t s) {
+vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, bool packed_table,
+                              const BatchArgs &b, const BruteArgs *d_recs, const uint32_t *d_item_end,
+                              int blocks, hipStream_t s) {
     if (b.n_items == 0) return VCM_OK;
     launch_zero_counter(b.counter, s);
     const dim3 grid(static_cast<unsigned>(blocks));
     dispatch<true>(ix.dim, fp64, ns, mode, b.stats != nullptr, [&](auto v) {
         using V = decltype(v);
-        hipLaunchKernelGGL((k_brute_batch<V::DIM, V::NS, V::E, V::MODE, V::ST>), grid, dim3(256), 0, s, b,
-                           d_recs, d_item_end, ix.dev.col_start, ix.dev.recs);
+        if (packed_table)
+            hipLaunchKernelGGL((k_brute_batch<V::DIM, V::NS, V::E, V::MODE, V::ST, kTabWave>), grid, dim3(256), 0,
+                               s, b, d_recs, d_item_end, ix.dev.col_start, ix.dev.recs);
+        else
+            hipLaunchKernelGGL((k_brute_batch<V::DIM, V::NS, V::E, V::MODE, V::ST, kTabNone>), grid, dim3(256), 0,
+                               s, b, d_recs, d_item_end, ix.dev.col_start, ix.dev.recs);
     });
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(VCM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));

@@ -193,9 +193,11 @@ BruteArgs make_brute_args(const Index &ix, const TargetDesc &t, const GridDesc &
                           const ParamDesc &p, const vcm_result &r, uint32_t *gate, int theta,
                           int chunk);
 void launch_zero_counter(unsigned *c, hipStream_t s);
-vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, const BatchArgs &b,
-                              const BruteArgs *d_recs, const uint32_t *d_item_end, int blocks,
-                              hipStream_t s);
+// packed_table: every target of the launch has half-extents below 4096 m
+// (sample offsets fit the wavefront tables' 21-bit fields).
+vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, bool packed_table,
+                              const BatchArgs &b, const BruteArgs *d_recs, const uint32_t *d_item_end,
+                              int blocks, hipStream_t s);
 
 // Pruned colouring (E / M / T) of every viewpoint from the block gates.
 vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g,
@@ -255,6 +257,7 @@ struct PlanGroup {
     bool fp64 = false;
     int mode = 0;
     int ns = 1;
+    bool packed_table = true;  // every target's half-extents below 4096 m
     std::vector<int> members;
     size_t rec_off = 0, end_off = 0, ctr_off = 0;
     uint32_t n_items = 0;
