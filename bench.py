@@ -183,7 +183,7 @@ def bench_serve(n_req: int):
            "requests": n_req, "mean_viewpoints": n_vp / n_req,
            "sequential_requests_per_s": n_req / t_seq, "index_cell_tuning": tuning, "rates": []}
     srv = vcm.Server(idx, max_inflight=2, max_batch=64)
-    for rate in (100.0, 250.0, 500.0, 1000.0, 4000.0):
+    for rate in (100.0, 250.0, 500.0, 1000.0, 4000.0, 16000.0):
         srv.reset_stats()
         arr = scenes.poisson_arrivals(rate, n_req, 55)
         tickets = []

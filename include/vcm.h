@@ -223,7 +223,8 @@ vcm_status vcm_compute_batch(const vcm_index *index, const vcm_query *queries, i
 typedef struct vcm_batch vcm_batch;
 
 typedef struct {
-    int32_t chunk;          /* viewpoints per work item, 1..64; 0 = default 8 */
+    int32_t chunk;          /* viewpoints per work item, 1..64; 0 = by mode
+                               (FULL 32, FRACTION 8)                         */
     int32_t blocks_per_cu;  /* persistent workgroups per CU, 1..16; 0 = default 8 */
     int32_t autotune;       /* 1: at creation, time the candidate shapes
                                (chunk 4/8/16/32 x 4/8 workgroups per CU) on a
@@ -234,7 +235,7 @@ typedef struct {
 } vcm_batch_opts;
 
 typedef struct {
-    int32_t chunk;
+    int32_t chunk;          /* 0: by mode                                    */
     int32_t blocks_per_cu;
     int32_t launches;       /* persistent ray launches per run              */
     int32_t graph;          /* 1 if runs replay a captured graph            */

@@ -154,7 +154,8 @@ void BatchPlan::layout() {
     for (size_t i = 0; i < q.size(); ++i) {
         const PlanQuery &pq = q[i];
         if (pq.g.count <= 0) continue;
-        const uint64_t it = query_items(pq, tune.chunk);
+        const uint64_t wi = query_items(pq, chunk_for(tune, pq.p.mode));
+        const uint64_t it = (wi + 3) / 4;  // groups of four work items (one workgroup claim)
         PlanGroup *g = nullptr;
         for (auto &x : groups)
             if (x.fp64 == (pq.p.fp64 != 0) && x.mode == pq.p.mode && x.n_items + it < kMaxItems) g = &x;
@@ -166,9 +167,8 @@ void BatchPlan::layout() {
         }
         g->members.push_back(static_cast<int>(i));
         g->ns = std::max(g->ns, pq.ns);
-        for (int k = 0; k < 3; ++k) g->packed_table = g->packed_table && pq.t.half[k] < 4096.0f;
         g->n_items += static_cast<uint32_t>(it);
-        items += it;
+        items += wi;
     }
     size_t off = 0;
     for (auto &g : groups) {
@@ -197,8 +197,9 @@ void BatchPlan::image(std::vector<char> &img) const {
             const PlanQuery &pq = q[g.members[m]];
             uint32_t *gate = pq.method == VCM_BRUTE ? nullptr
                                                     : reinterpret_cast<uint32_t *>(d_base + pq.gate_off);
-            recs[m] = make_brute_args(*ix, pq.t, pq.g, pq.p, pq.r, gate, pq.theta, tune.chunk);
-            acc += static_cast<uint32_t>(query_items(pq, tune.chunk));
+            const int chunk = chunk_for(tune, pq.p.mode);
+            recs[m] = make_brute_args(*ix, pq.t, pq.g, pq.p, pq.r, gate, pq.theta, chunk);
+            acc += static_cast<uint32_t>((query_items(pq, chunk) + 3) / 4);
             ends[m] = acc;
         }
     }
@@ -212,8 +213,8 @@ vcm_status BatchPlan::enqueue(hipStream_t s, DevStats *stats) const {
         b.stats = stats;
         b.nq = static_cast<int32_t>(g.members.size());
         b.n_items = g.n_items;
-        const int64_t blocks = std::min<int64_t>((int64_t(g.n_items) + 3) / 4, int64_t(cus) * tune.blocks_per_cu);
-        vcm_status st = launch_brute_batch(*ix, g.fp64, g.mode, g.ns, g.packed_table, b,
+        const int64_t blocks = std::min<int64_t>(int64_t(g.n_items), int64_t(cus) * tune.blocks_per_cu);
+        vcm_status st = launch_brute_batch(*ix, g.fp64, g.mode, g.ns, b,
                                            reinterpret_cast<const BruteArgs *>(d_base + g.rec_off),
                                            reinterpret_cast<const uint32_t *>(d_base + g.end_off),
                                            static_cast<int>(std::max<int64_t>(blocks, 1)), s);

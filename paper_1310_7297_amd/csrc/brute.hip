@@ -189,34 +189,8 @@ __device__ void build_sample_table(const TargetDesc &T, float4 *tab) {
     __syncthreads();
 }
 
-// Sample sources: lattice arithmetic, the workgroup's float table, or a
-// wavefront's packed table (batched launches, whose wavefronts may serve
-// different queries).
-constexpr int kTabNone = 0, kTabBlock = 1, kTabWave = 2;
-
-// Packed table of one wavefront: per sample, its offsets from the target
-// centre in units of 2^-8 m as three signed 21-bit fields of 64 bits (exact
-// for targets of half-extent below 4096 m, which the host checks).  Written
-// and read by the same wavefront.
-template <int DIM>
-__device__ void build_wave_table(const TargetDesc &T, uint2 *tab) {
-    const int lane = threadIdx.x & 63;
-    const int n = (T.kind == VCM_CUBE ? 6 : 1) * T.per_facet;
-    for (int t = lane; t < n && t < kTableMax; t += 64) {
-        const unsigned fc = static_cast<unsigned>((static_cast<unsigned>(t) * T.m_pf) >> 32);
-        const unsigned w = static_cast<unsigned>(t) - fc * T.per_facet;
-        float sp[3];
-        sample_pos_face<DIM>(T, fc, w, sp);
-        const long long ox = static_cast<int>((sp[0] - T.c[0]) * 256.0f) & 0x1fffff;
-        const long long oy = static_cast<int>((sp[1] - T.c[1]) * 256.0f) & 0x1fffff;
-        const long long oz = DIM == 3 ? static_cast<int>((sp[2] - T.c[2]) * 256.0f) & 0x1fffff : 0;
-        const long long v = ox | (oy << 21) | (oz << 42);
-        tab[t] = make_uint2(static_cast<unsigned>(v), static_cast<unsigned>(v >> 32));
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+// Sample sources: lattice arithmetic, or the workgroup's table.
+constexpr int kTabNone = 0, kTabBlock = 1;
 
 // Position of sample `si` among the live samples of a viewpoint whose live
 // facets are `faces` (cube, packed 4 bits per live face) or the single facet
@@ -232,16 +206,6 @@ __device__ __attribute__((always_inline)) inline void sample_pos(const TargetDes
         s[0] = p.x;
         s[1] = p.y;
         s[2] = p.z;
-    } else if (TAB == kTabWave) {
-        // three signed 21-bit offsets from the target centre, in 2^-8 m
-        const uint2 e = static_cast<const uint2 *>(tab)[fc * T.per_facet + w];
-        const long long v = static_cast<long long>(e.x) | (static_cast<long long>(e.y) << 32);
-        const int ox = static_cast<int>((v << 43) >> 43);
-        const int oy = static_cast<int>((v << 22) >> 43);
-        const int oz = static_cast<int>((v << 1) >> 43);
-        s[0] = T.c[0] + static_cast<float>(ox) * 0x1p-8f;
-        s[1] = T.c[1] + static_cast<float>(oy) * 0x1p-8f;
-        s[2] = DIM == 3 ? T.c[2] + static_cast<float>(oz) * 0x1p-8f : 0.0f;
     } else {
         sample_pos_face<DIM>(T, fc, w, s);
     }
@@ -752,7 +716,7 @@ __device__ inline void flush_stats(DevStats *st, const WaveStats &ws, unsigned l
 
 // One query: persistent wavefronts take the query's work items.
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_brute(BruteArgs A, const int32_t *col_start_g,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_brute(BruteArgs A, const int32_t *col_start_g,
                                                const BoxRec *recs_g) {
     // same kernel symbol in both compiler passes; constant-space view inside
     const cptr_i32 col_start = (cptr_i32)col_start_g;
@@ -773,46 +737,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 }
 
 // Many queries on one index in one launch.  The work items of all queries
-// form one list (query after query); a wavefront finds the query of an item
-// by binary search over the queries' item ends and reads the query's record
+// form one list (query after query) in groups of four items of one query.  A
+// workgroup claims a group, one item per wavefront, so that its wavefronts
+// share one sample table in LDS, rebuilt when the workgroup moves to another
+// query; neighbouring viewpoints cost about the same, so the wavefronts wait
+// little for one another at the end of a group.  The query of a group is
+// found by binary search over the queries' group ends; its record is read
 // from constant memory (scalar loads).
-template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_brute_batch(
-    BatchArgs B, const BruteArgs *qs_g, const uint32_t *item_end_g, const int32_t *col_start_g,
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_brute_batch(
+    BatchArgs B, const BruteArgs *qs_g, const uint32_t *group_end_g, const int32_t *col_start_g,
     const BoxRec *recs_g) {
     const cptr_i32 col_start = (cptr_i32)col_start_g;
     const cptr_rec recs = (cptr_rec)recs_g;
     const VCM_CONST BruteArgs *qs = (const VCM_CONST BruteArgs *)qs_g;
-    const VCM_CONST uint32_t *item_end = (const VCM_CONST uint32_t *)item_end_g;
+    const VCM_CONST uint32_t *group_end = (const VCM_CONST uint32_t *)group_end_g;
     __shared__ int lds_rays[4][kMaxSamples];
-    __shared__ uint2 s_wtab[TAB == kTabWave ? 4 : 1][TAB == kTabWave ? kTableMax : 1];
+    __shared__ float4 s_tab[kTableMax];
+    __shared__ unsigned s_group;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int *lds = lds_rays[wave];
-    uint2 *wtab = s_wtab[TAB == kTabWave ? wave : 0];
-    int cur_q = -1;  // query whose samples the wavefront's table holds
+    int cur_q = -1;  // query whose samples the table holds (workgroup-uniform)
     WaveStats ws;
     unsigned long long n_disagree = 0;
-    Dispenser D;
+    Dispenser D;  // claims by wavefront 0 for the workgroup
     D.init(B.counter, B.n_items);
-    unsigned item;
-    while (D.next(item)) {
+    for (;;) {
+        if (wave == 0) {
+            unsigned g = 0;
+            const bool got = D.next(g);
+            if ((threadIdx.x & 63) == 0) s_group = got ? g : 0xffffffffu;
+        }
+        __syncthreads();
+        const unsigned group = __builtin_amdgcn_readfirstlane(s_group);
+        if (group == 0xffffffffu) break;
         int lo = 0, hi = B.nq - 1;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (item_end[mid] > item) hi = mid;
+            if (group_end[mid] > group) hi = mid;
             else lo = mid + 1;
         }
-        const unsigned begin = lo > 0 ? item_end[lo - 1] : 0u;
+        const unsigned begin = lo > 0 ? group_end[lo - 1] : 0u;
         // a generic reference derived from the constant-space pointer: the
         // compiler turns the field reads back into scalar constant loads
         // (a local copy of the record would live in scratch memory)
         const BruteArgs &A = *reinterpret_cast<const BruteArgs *>(qs + lo);
-        if (TAB == kTabWave && lo != cur_q) {
-            build_wave_table<DIM>(A.tgt, wtab);
+        if (lo != cur_q) {
+            build_sample_table<DIM>(A.tgt, s_tab);  // ends with a workgroup barrier
             cur_q = lo;
         }
-        run_item<DIM, NS, EXACT64, MODE, STATS, TAB>(A, col_start, recs, item - begin, lds, wtab, ws,
-                                                      n_disagree);
+        const unsigned item = (group - begin) * 4u + static_cast<unsigned>(wave);
+        if (item < A.n_items)
+            run_item<DIM, NS, EXACT64, MODE, STATS, kTabBlock>(A, col_start, recs, item, lds, s_tab, ws,
+                                                                n_disagree);
+        __syncthreads();  // the table and s_group are reused next round
     }
     flush_stats<STATS>(B.stats, ws, n_disagree);
 }
@@ -929,20 +907,16 @@ void launch_zero_counter(unsigned *c, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, c);
 }
 
-vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, bool packed_table,
-                              const BatchArgs &b, const BruteArgs *d_recs, const uint32_t *d_item_end,
-                              int blocks, hipStream_t s) {
+vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, const BatchArgs &b,
+                              const BruteArgs *d_recs, const uint32_t *d_group_end, int blocks,
+                              hipStream_t s) {
     if (b.n_items == 0) return VCM_OK;
     launch_zero_counter(b.counter, s);
     const dim3 grid(static_cast<unsigned>(blocks));
     dispatch<true>(ix.dim, fp64, ns, mode, b.stats != nullptr, [&](auto v) {
         using V = decltype(v);
-        if (packed_table)
-            hipLaunchKernelGGL((k_brute_batch<V::DIM, V::NS, V::E, V::MODE, V::ST, kTabWave>), grid, dim3(256), 0,
-                               s, b, d_recs, d_item_end, ix.dev.col_start, ix.dev.recs);
-        else
-            hipLaunchKernelGGL((k_brute_batch<V::DIM, V::NS, V::E, V::MODE, V::ST, kTabNone>), grid, dim3(256), 0,
-                               s, b, d_recs, d_item_end, ix.dev.col_start, ix.dev.recs);
+        hipLaunchKernelGGL((k_brute_batch<V::DIM, V::NS, V::E, V::MODE, V::ST>), grid, dim3(256), 0, s, b,
+                           d_recs, d_group_end, ix.dev.col_start, ix.dev.recs);
     });
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(VCM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -953,7 +927,7 @@ vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_
                         const ParamDesc &p, const vcm_result &r, hipStream_t stream,
                         DevStats *stats, uint32_t *gate, int theta, const Tuning &tune) {
     if (g_in.count <= 0) return VCM_OK;
-    BruteArgs a = make_brute_args(ix, t, g_in, p, r, gate, theta, tune.chunk);
+    BruteArgs a = make_brute_args(ix, t, g_in, p, r, gate, theta, chunk_for(tune, p.mode));
     a.stats = stats;
     const int ns = slots_for(t);
     if (ns < 1 || ns > kMaxSlots) return set_error(VCM_E_INVALID, "too many target samples");

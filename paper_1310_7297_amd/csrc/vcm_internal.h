@@ -139,9 +139,17 @@ struct BatchArgs {
 
 // Launch shape of the ray kernels.
 struct Tuning {
-    int chunk = 8;          // viewpoints per work item
+    int chunk = 0;          // viewpoints per work item; 0: by mode (chunk_for)
     int blocks_per_cu = 8;  // persistent workgroups (4 wavefronts each) per CU
 };
+
+// Viewpoints per work item.  FULL-mode viewpoints are cheap and reuse the
+// previous viewpoint's blocker, so they take longer runs; FRACTION-mode ones
+// balance better in short runs.
+inline int chunk_for(const Tuning &t, int mode) {
+    if (t.chunk > 0) return t.chunk;
+    return mode == VCM_FULL ? 32 : 8;
+}
 
 // Host-side index object behind the opaque vcm_index handle.
 struct Index {
@@ -193,11 +201,11 @@ BruteArgs make_brute_args(const Index &ix, const TargetDesc &t, const GridDesc &
                           const ParamDesc &p, const vcm_result &r, uint32_t *gate, int theta,
                           int chunk);
 void launch_zero_counter(unsigned *c, hipStream_t s);
-// packed_table: every target of the launch has half-extents below 4096 m
-// (sample offsets fit the wavefront tables' 21-bit fields).
-vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, bool packed_table,
-                              const BatchArgs &b, const BruteArgs *d_recs, const uint32_t *d_item_end,
-                              int blocks, hipStream_t s);
+// d_group_end: per query, the end of its groups of four work items in the
+// launch's list (b.n_items counts groups).
+vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, const BatchArgs &b,
+                              const BruteArgs *d_recs, const uint32_t *d_group_end, int blocks,
+                              hipStream_t s);
 
 // Pruned colouring (E / M / T) of every viewpoint from the block gates.
 vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g,
@@ -257,10 +265,9 @@ struct PlanGroup {
     bool fp64 = false;
     int mode = 0;
     int ns = 1;
-    bool packed_table = true;  // every target's half-extents below 4096 m
     std::vector<int> members;
     size_t rec_off = 0, end_off = 0, ctr_off = 0;
-    uint32_t n_items = 0;
+    uint32_t n_items = 0;  // groups of four work items
 };
 
 // Device layout and launch sequence of a batch:
