@@ -640,8 +640,12 @@ __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &
         }
         float q[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 3; ++k) {
             q[k] = (k < DIM) ? A.grid.o[k] + static_cast<float>(2 * ii[k] + 1) * A.grid.h2[k] : 0.0f;
+            // FRACTION mode keeps more rays live: q in scalar registers
+            // leaves vector registers to them (measured: less spilling)
+            if (MODE == VCM_FRACTION) q[k] = uniform_f(q[k]);
+        }
         // live facets packed 4 bits each: cube faces whose outer side
         // contains q strictly (code 2k+1 for +k, 2k for -k)
         unsigned faces = 0;
@@ -714,9 +718,16 @@ __device__ inline void flush_stats(DevStats *st, const WaveStats &ws, unsigned l
     if (n_disagree) atomicAdd(&st->fp32_disagree, n_disagree);  // per lane
 }
 
+// Occupancy target of the ray kernels (waves per SIMD): the register budget
+// it leaves decides how much the compiler spills.  FULL mode gains from the
+// seventh wave; FRACTION mode, whose walk keeps more rays and masks live,
+// spills to scratch memory at seven.
+template <int MODE>
+constexpr int kWaves = MODE == VCM_FULL ? 7 : 6;
+
 // One query: persistent wavefronts take the query's work items.
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_brute(BruteArgs A, const int32_t *col_start_g,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE>, 8))) void k_brute(BruteArgs A, const int32_t *col_start_g,
                                                const BoxRec *recs_g) {
     // same kernel symbol in both compiler passes; constant-space view inside
     const cptr_i32 col_start = (cptr_i32)col_start_g;
@@ -745,7 +756,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
 // found by binary search over the queries' group ends; its record is read
 // from constant memory (scalar loads).
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_brute_batch(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE>, 8))) void k_brute_batch(
     BatchArgs B, const BruteArgs *qs_g, const uint32_t *group_end_g, const int32_t *col_start_g,
     const BoxRec *recs_g) {
     const cptr_i32 col_start = (cptr_i32)col_start_g;
