@@ -28,7 +28,7 @@ PEAK_HBM = 8.0e12
 # FETCH_SIZE / WRITE_SIZE summary (copy-kernel calibrated), valid only for the
 # kernel sources it was taken on.
 PROFILE = os.path.join(ROOT, "profiles", "k_brute_city20k_cube_fraction.md")
-TRAFFIC_BYTES = 77201377
+TRAFFIC_BYTES = 87362790
 TRAFFIC_CELL = 64.0
 KERNEL_SOURCES = ("brute.hip", "index.hip", "vcm_internal.h")
 
