@@ -69,6 +69,7 @@ def parse():
                     help="time the headline map only (no other mode, batch or serving legs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (config 4) leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (config 5) leg")
+    ap.add_argument("--no-pruned", action="store_true", help="skip the pruned-construction leg")
     ap.add_argument("--serve-requests", type=int, default=240)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
@@ -105,6 +106,50 @@ def timed_steps(vcm, idx, q, bufs, steps, warmup):
     wall = time.perf_counter() - t0
     kms = [e0.elapsed_time(e1) for e0, e1 in evs]
     return wall, kms
+
+
+def bench_pruned(vcm, idx, q):
+    """Config 3: the pruned construction (VCM_E, VCM_M, VCM_T) beside the
+    brute-force map, FULL mode (the paper's rule): time per map, the Sec. V-A
+    error of VCM_E against the brute force and of VCM_M / VCM_T against
+    VCM_E, the Sec. IV-A bounds, and VCM_E over minimum block sizes."""
+    import torch
+    from paper_1310_7297_amd import scenes
+    n = q.grid.count
+
+    def with_(**kw):
+        return scenes.Query(q.target, q.grid, scenes.Params(**{**q.params.__dict__, **kw}))
+
+    def run(qq, reps=3):
+        r = vcm.alloc_result(n)
+        vcm.vcm_compute(idx, qq, *r)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            vcm.vcm_compute(idx, qq, *r)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return r, min(ms)
+
+    brute, t_b = run(with_(mode=scenes.FULL, method=scenes.BRUTE))
+    out = {"mode": "full", "brute_ms": t_b, "methods": {}, "theta": {}}
+    maps = {}
+    for name, m in (("E", scenes.PRUNED_E), ("M", scenes.PRUNED_M), ("T", scenes.PRUNED_T)):
+        r, t = run(with_(mode=scenes.FULL, method=m))
+        maps[name] = r
+        ref = brute if name == "E" else maps["E"]
+        err = vcm.vcm_map_error(ref[1], r[1])
+        out["methods"][name] = {"ms": t, "error_vs": "brute" if name == "E" else "E",
+                                "error_signed": err[0], "error_abs": err[1]}
+    out["bounds"] = vcm.vcm_error_bounds(q, 3)
+    for th in (2, 4, 8, 16):
+        r, t = run(with_(mode=scenes.FULL, method=scenes.PRUNED_E, theta_blocks=th))
+        err = vcm.vcm_map_error(maps["E"][1], r[1])
+        out["theta"][str(th)] = {"ms": t, "error_signed_vs_theta1": err[0], "error_abs_vs_theta1": err[1]}
+    return out
 
 
 def bench_batch():
@@ -286,6 +331,10 @@ def main():
                                "viewpoints_per_s": n_vp * max(2, args.steps // 2) / w2,
                                "kernel_ms": float(np.mean(k2))}
 
+    if not (args.no_pruned or args.no_extra) and args.config == 3:
+        extra["pruned"] = bench_pruned(vcm, idx, q)
+        print("pruned: " + ", ".join(f"{k} {v['ms']:.2f} ms" for k, v in extra["pruned"]["methods"].items()),
+              file=sys.stderr, flush=True)
     if not (args.no_batch or args.no_extra):
         extra["batch"] = bench_batch()
         print(f"batch: {extra['batch']['speedup_vs_sequential']:.2f}x sequential", file=sys.stderr,

@@ -53,6 +53,25 @@ struct Ring {
     int L;
 };
 
+// An upper bound on the angular width of every band of every ring whose
+// middle distance d' lies in [a, b].  Band edges are (pi/2)(2d'/S) tan(W/2)
+// with W stepping by mu, and tan is convex, so a ring's widest regular band
+// is its first, of width (pi/2) t (x + 1/x) / (1 + x t) with x = S/(2d'),
+// t = tan(mu/2); its last band is narrower than (pi/2)(2d'/S) tan(mu); a ring
+// with W0 < 2 mu is one band of pi/2.  The bound decreases and then increases
+// with d', so on an interval it is largest at an end.
+__device__ inline double band_bound(const CellFrame &F, double d) {
+    const double W0 = 2.0 * atan(F.S / (2.0 * d));
+    if (W0 < 2.0 * F.mu) return M_PI / 2.0;
+    const double x = F.S / (2.0 * d), t = tan(F.mu / 2.0);
+    const double first = (M_PI / 2.0) * t * (x + 1.0 / x) / (1.0 + x * t);
+    const double last = (M_PI / 2.0) * (2.0 * d / F.S) * tan(F.mu);
+    return fmax(first, last);
+}
+__device__ inline double widest_band(const CellFrame &F, double a, double b) {
+    return fmin(M_PI / 2.0, 1.000001 * fmax(band_bound(F, a), band_bound(F, b)) + 1e-12);
+}
+
 __device__ inline Ring make_ring(const CellFrame &F, int i) {
     Ring r;
     r.dl = ring_d(F, i);
@@ -176,6 +195,14 @@ __global__ __launch_bounds__(256) void k_pruned(PrunedArgs A) {
             int i0 = ring_of(F, D / sqrt(2.0));
             i0 = i0 < 0 ? 0 : i0;
             while (i0 > 0 && sqrt(2.0) * ring_d(F, i0) >= D) --i0;
+            // tighter: with u = sin g_j, v = cos g_{j+1} of a band of width w,
+            // u^2 + v^2 <= 1 + 2w, so a ring whose MBR holds q has
+            // D^2 <= d_{i+1}^2 (1 + 2w)
+            {
+                const double w = widest_band(F, ring_d(F, i0), ring_d(F, iq + 1));
+                const int i1 = ring_of(F, D / sqrt(1.0 + 2.0 * w)) - 1;
+                if (i1 > i0) i0 = i1;
+            }
             bool found = false;
             for (int i = i0; i <= iq && !found; ++i) {
                 if (sqrt(2.0) * ring_d(F, i + 1) < D) continue;
@@ -203,6 +230,13 @@ __global__ __launch_bounds__(256) void k_pruned(PrunedArgs A) {
             int i0 = ring_of(F, D * sqrt(0.5));
             i0 = i0 < 0 ? 0 : i0;
             while (i0 > 0 && ring_d(F, i0) > D * sqrt(0.5)) --i0;
+            // tighter: alpha lies in the band, within half a band width of its
+            // middle, so the projection is at least D cos(w / 2)
+            {
+                const double w = widest_band(F, ring_d(F, i0), ring_d(F, iq + 1));
+                const int i1 = ring_of(F, D * cos(0.5 * w)) - 1;
+                if (i1 > i0) i0 = i1;
+            }
             bool found = false;
             for (int i = i0; i <= iq && !found; ++i) {
                 const Ring r = make_ring(F, i);
