@@ -16,7 +16,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic VALU lane-operations per unit of work (see the design notes):
+# Algorithmic VALU lane-operations per unit of work:
 # one float32 slab test of a ray against a box, and one corridor column visit.
 OPS_PER_BOX_TEST = 20
 OPS_PER_COLUMN = 12
@@ -42,9 +42,9 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(config: int, mode: str, cell: float):
+def measured_traffic(workload: str, mode: str, cell: float):
     """The profiled HBM bytes, or None if the workload or the kernel differs."""
-    if config != 3 or mode != "fraction" or cell != TRAFFIC_CELL:
+    if workload != "cube" or mode != "fraction" or cell != TRAFFIC_CELL:
         return None
     try:
         text = open(PROFILE).read()
@@ -58,7 +58,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=3, choices=(2, 3))
+    ap.add_argument("--workload", default="cube", choices=("cube", "billboard"),
+                    help="cube: 4 km city, 20,000 boxes, 30 m cube; billboard: 2 km city, 5,000 boxes")
     ap.add_argument("--mode", default="fraction", choices=("fraction", "full"))
     ap.add_argument("--cell", type=float, default=-1.0,
                     help="index column width; -1 (default): autotuned over 32/64/128 m for this "
@@ -67,8 +68,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="time the headline map only (no other mode, batch or serving legs)")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched (config 4) leg")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving (config 5) leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg (256 targets, 6.4 km city)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg (8 km city, Poisson arrivals)")
     ap.add_argument("--no-pruned", action="store_true", help="skip the pruned-construction leg")
     ap.add_argument("--serve-requests", type=int, default=240)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -109,7 +110,7 @@ def timed_steps(vcm, idx, q, bufs, steps, warmup):
 
 
 def bench_pruned(vcm, idx, q):
-    """Config 3: the pruned construction (VCM_E, VCM_M, VCM_T) beside the
+    """4 km cube map: the pruned construction (VCM_E, VCM_M, VCM_T) beside the
     brute-force map, FULL mode (the paper's rule): time per map, the Sec. V-A
     error of VCM_E against the brute force and of VCM_M / VCM_T against
     VCM_E, the Sec. IV-A bounds, and VCM_E over minimum block sizes."""
@@ -153,13 +154,13 @@ def bench_pruned(vcm, idx, q):
 
 
 def bench_batch():
-    """Config 4: 256 targets on a shared 50,000-box city, grids 32x32x16 to
+    """Batched: 256 targets on a shared 50,000-box city, grids 32x32x16 to
     256x256x64.  One prepared batch (autotuned launch shape, HIP graph) against
     the same 256 queries as sequential vcm_compute calls; results identical."""
     import torch
     import paper_1310_7297_amd as vcm
     from paper_1310_7297_amd import scenes
-    scene, qs = scenes.config4()
+    scene, qs = scenes.city6km_batch256()
     tuning = vcm.vcm_tune_cell_size(scene, qs[::8], cell_min=16.0, cell_max=64.0, reps=1)
     idx = vcm.vcm_build_index(scene, cell_size=tuning["best_cell"])
     n_vp = sum(q.grid.count for q in qs)
@@ -190,7 +191,7 @@ def bench_batch():
     same = all(torch.equal(x, y) for a, r in zip(seq, res) for x, y in zip(a, r))
     b.close()
     idx.free()
-    return {"workload": "config4: 256 billboards/cubes (5-40 m), 50,000-box 6.4 km city, "
+    return {"workload": "city6km_batch256: 256 billboards/cubes (5-40 m), 50,000-box 6.4 km city, "
                         "grids 32x32x16..256x256x64",
             "viewpoints": n_vp, "sequential_viewpoints_per_s": n_vp / t_seq,
             "batched_viewpoints_per_s": n_vp / t_batch,
@@ -202,14 +203,14 @@ def bench_batch():
 
 
 def bench_serve(n_req: int):
-    """Config 5: Poisson arrivals over a resident 100,000-box 8 km city; grids
+    """Serving: Poisson arrivals over a resident 100,000-box 8 km city; grids
     64x64x16 / 128x128x32 / 256x256x64 (0.6/0.3/0.1).  p50/p99 latency and
     throughput per arrival rate, and the same requests as sequential calls."""
     import threading
     import torch
     import paper_1310_7297_amd as vcm
     from paper_1310_7297_amd import scenes
-    scene, qs = scenes.config5(n_requests=n_req)
+    scene, qs = scenes.city8km_serving(n_requests=n_req)
     tuning = vcm.vcm_tune_cell_size(scene, qs[:32], cell_min=16.0, cell_max=64.0, reps=1)
     idx = vcm.vcm_build_index(scene, cell_size=tuning["best_cell"])
     res = [vcm.alloc_result(q.grid.count) for q in qs]
@@ -223,7 +224,7 @@ def bench_serve(n_req: int):
         vcm.vcm_compute(idx, q, *r)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    out = {"workload": "config5: 100,000-box 8 km city, Poisson arrivals, grids 64x64x16 / "
+    out = {"workload": "city8km_serving: 100,000-box 8 km city, Poisson arrivals, grids 64x64x16 / "
                        "128x128x32 / 256x256x64 (0.6/0.3/0.1)",
            "requests": n_req, "mean_viewpoints": n_vp / n_req,
            "sequential_requests_per_s": n_req / t_seq, "index_cell_tuning": tuning, "rates": []}
@@ -269,16 +270,15 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by viewpoint tiles with no exchange; see the design notes)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the maps "
+              "would shard by viewpoint ranges with no exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
     import paper_1310_7297_amd as vcm
     from paper_1310_7297_amd import scenes
 
-    cfg = scenes.config3 if args.config == 3 else scenes.config2
+    cfg = scenes.city4km_cube if args.workload == "cube" else scenes.city2km_billboard
     scene, q = cfg()
     mode = scenes.FRACTION if args.mode == "fraction" else scenes.FULL
     q.params.mode = mode
@@ -311,7 +311,7 @@ def main():
     achieved = ops / (kernel_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS,
-                "traffic": measured_traffic(args.config, args.mode, info["cell_size"]),
+                "traffic": measured_traffic(args.workload, args.mode, info["cell_size"]),
                 "kernel": "k_brute", "kernel_ms": kernel_ms,
                 "box_tests_per_launch": st["box_tests"], "columns_per_launch": st["columns"],
                 "rechecks_per_launch": st["rechecks"],
@@ -331,7 +331,7 @@ def main():
                                "viewpoints_per_s": n_vp * max(2, args.steps // 2) / w2,
                                "kernel_ms": float(np.mean(k2))}
 
-    if not (args.no_pruned or args.no_extra) and args.config == 3:
+    if not (args.no_pruned or args.no_extra) and args.workload == "cube":
         extra["pruned"] = bench_pruned(vcm, idx, q)
         print("pruned: " + ", ".join(f"{k} {v['ms']:.2f} ms" for k, v in extra["pruned"]["methods"].items()),
               file=sys.stderr, flush=True)
@@ -353,6 +353,14 @@ def main():
                "sample": f"{len(vp)} seeded uniform-random viewpoints of the same grid and mode, "
                          f"single thread, {dt:.1f} s",
                "rays_per_s": float(o["nlive"][o["infov"] > 0].astype(np.int64).sum()) / dt}
+        # the same oracle split over the host's cores (reported beside it)
+        ncores = min(16, len(os.sched_getaffinity(0)))
+        t0 = time.perf_counter()
+        oracle.vcm_eval(scene, q, vp, nthreads=ncores)
+        dt_all = time.perf_counter() - t0
+        extra["cpu_baseline_all_cores"] = {"value": len(vp) / dt_all, "unit": "viewpoints/s",
+                                           "cores": ncores, "kind": "oracle",
+                                           "sample": f"the same {len(vp)} viewpoints, {ncores} threads"}
 
     line = {
         "metric": "VCM viewpoints/s (brute-force map, 3D city)",
@@ -367,10 +375,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64recheck",
         "data": "synthetic",
-        "config": {"workload": f"config{args.config}: "
-                   + ("4 km city, 20,000 boxes, 30 m cube 8x8/face, 256x256x64 viewpoints"
-                      if args.config == 3 else
-                      "2 km city, 5,000 boxes, 10x5 m billboard 16x8, 128x128x32 viewpoints"),
+        "config": {"workload": ("city4km_cube: 4 km city, 20,000 boxes, 30 m cube 8x8/face, "
+                                "256x256x64 viewpoints" if args.workload == "cube" else
+                                "city2km_billboard: 2 km city, 5,000 boxes, 10x5 m billboard 16x8, "
+                                "128x128x32 viewpoints"),
                    "mode": args.mode, "viewpoints": n_vp, "boxes": scene.n, "n_bins": q.params.n_bins,
                    "cell_size": info["cell_size"], "parallelism": "single-gpu"},
         "rays_per_s": rays_ps,

@@ -22,7 +22,7 @@
  *   - Field of view (Sec. III-B): viewpoints outside the FOV wedge around the
  *     target normal are obstructed.
  *
- * Readings taken where the paper is silent (all listed in the design notes):
+ * Readings taken where the paper is silent:
  *   - S is the largest target dimension; D is the distance from the viewpoint
  *     to the target centre, floored at the near point d0; alpha is the angle
  *     between the line of sight and the target plane, measured in the

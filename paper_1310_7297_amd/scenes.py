@@ -219,9 +219,9 @@ def random_boxes(n: int, seed: int, extent=64.0, max_side=16.0, dim=3,
     return Scene(dim, quantize(lo), quantize(hi))
 
 
-# ---------------------------------------------------------------- configs ---
+# -------------------------------------------------------------- workloads ---
 
-def config1():
+def plain2d_50rects():
     """2-D plain: 1000 x 1000, 50 rectangles, segment target, 64 x 64 grid."""
     t = Target(SEGMENT, (500.0, 500.0, 0.0), (40.0, 0.0), normal_axis=1,
                normal_sign=1, samples_u=32, samples_v=1)
@@ -231,7 +231,7 @@ def config1():
     return scene, Query(t, g, p)
 
 
-def config2():
+def city2km_billboard():
     """3-D plain: 2 km city, 5,000 boxes, 10 x 5 m billboard, 128x128x32."""
     t = Target(BILLBOARD, (1000.0, 1000.0, 12.5), (10.0, 5.0), normal_axis=1,
                normal_sign=1, samples_u=16, samples_v=8)
@@ -241,7 +241,7 @@ def config2():
     return scene, Query(t, g, p)
 
 
-def config3():
+def city4km_cube():
     """3-D pruned vs brute: 4 km city, 20,000 boxes, 30 m cube, 256x256x64."""
     t = Target(CUBE, (2000.0, 2000.0, 15.0), (30.0, 0.0), samples_u=8, samples_v=8)
     scene = city(4000.0, 20000, seed=3, targets=[t])
@@ -277,7 +277,7 @@ def _batch_targets(rng, n, city_extent, window):
     return queries
 
 
-def config4(n_targets: int = 256):
+def city6km_batch256(n_targets: int = 256):
     """Batched: 50,000-box 6.4 km city shared by 256 targets of mixed kind and size."""
     rng = np.random.Generator(np.random.PCG64(4))
     queries = _batch_targets(rng, n_targets, 6400.0, 2560.0)
@@ -285,7 +285,7 @@ def config4(n_targets: int = 256):
     return scene, queries
 
 
-def config5(n_requests: int = 2000):
+def city8km_serving(n_requests: int = 2000):
     """Serving: 100,000-box 8 km city; queries with grids 64^2x16/128^2x32/256^2x64."""
     rng = np.random.Generator(np.random.PCG64(55))
     queries = _batch_targets(rng, n_requests, 8000.0, 3072.0)

@@ -66,7 +66,7 @@ def test_every_kernel_stub_has_device_code():
         assert any(s in k for k in syms), s
 
 
-@pytest.mark.parametrize("cfg,dim", [("config1", 2), ("config2", 3), ("config3", 3)])
+@pytest.mark.parametrize("cfg,dim", [("plain2d_50rects", 2), ("city2km_billboard", 3), ("city4km_cube", 3)])
 def test_error_bounds_match_oracle(cfg, dim):
     """vcm_error_bounds is a host computation; it equals the oracle's sums."""
     import math
@@ -86,7 +86,7 @@ def test_error_bounds_match_oracle(cfg, dim):
 
 def test_tune_cell_size_rejects_bad_widths():
     """Argument checks of the index autotuner precede any device work."""
-    scene, q = scenes.config1()
+    scene, q = scenes.plain2d_50rects()
     for kw in ({"cell_min": 24.0}, {"cell_min": 64.0, "cell_max": 32.0}, {"cell_max": 8192.0},
                {"reps": 101}):
         with pytest.raises(vcm.VcmError) as e:
@@ -94,3 +94,15 @@ def test_tune_cell_size_rejects_bad_widths():
         assert e.value.status == vcm.VCM_E_INVALID
     with pytest.raises(vcm.VcmError):
         vcm.vcm_tune_cell_size(scene, [], cell_min=16.0)
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark runs on one GPU; asking for more exits with a message
+    before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr

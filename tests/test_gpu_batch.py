@@ -153,11 +153,11 @@ def test_empty_batch_and_rejects():
     idx.free()
 
 
-def test_config4_batch_equals_solo_and_oracle():
+def test_city6km_batch256_equals_solo_and_oracle():
     """256 targets of mixed kind and size on a shared 50,000-box city, grids
-    from 32x32x16 to 256x256x64 (config 4), in one batched launch."""
+    from 32x32x16 to 256x256x64, in one batched launch."""
     import torch
-    scene, qs = scenes.config4()
+    scene, qs = scenes.city6km_batch256()
     idx = vcm.vcm_build_index(scene)
     res = [vcm.alloc_result(q.grid.count) for q in qs]
     b = vcm.Batch(idx, qs, res, autotune=True, use_graph=True)
@@ -166,7 +166,7 @@ def test_config4_batch_equals_solo_and_oracle():
     rng = np.random.default_rng(44)
     for i in range(len(qs)):
         one = _solo(idx, qs[i])
-        _same(one, res[i], f"config4 query {i}")
+        _same(one, res[i], f"city6km_batch256 query {i}")
         del one
     for i in rng.choice(len(qs), 6, replace=False):
         q = qs[i]

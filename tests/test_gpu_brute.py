@@ -56,12 +56,12 @@ def _near_target(grid, target, radius, limit, seed):
 @pytest.mark.parametrize("precision", [vcm.VCM_FP64, vcm.VCM_FP32_RECHECK])
 @pytest.mark.parametrize("mode", [FULL, FRACTION])
 @pytest.mark.parametrize("scale", [0, BIN_LOG])
-def test_config1_full_map(precision, mode, scale):
-    scene, q = scenes.config1()
+def test_plain2d_full_map(precision, mode, scale):
+    scene, q = scenes.plain2d_50rects()
     q = _with(q, mode=mode, bin_scale=scale)
     g = _gpu_map(scene, q, precision=precision)
     o = oracle.vcm_eval(scene, q)
-    compare(g, o, q.params.n_bins, label=f"config1 p{precision} m{mode} s{scale}")
+    compare(g, o, q.params.n_bins, label=f"plain2d_50rects p{precision} m{mode} s{scale}")
     assert (o["count"] > 0).sum() > 100
 
 
@@ -111,7 +111,7 @@ def test_empty_scene_and_single_viewpoint():
         compare(_gpu_map(sc, q), oracle.vcm_eval(sc, q), 16, label="empty")
 
 
-# ---------------------------------------------------------------- 3-D configs --
+# ---------------------------------------------------------- 3-D workloads --
 
 def _sampled(cfg, mode, n_random, n_near, radius, seed):
     scene, q = cfg()
@@ -126,19 +126,19 @@ def _sampled(cfg, mode, n_random, n_near, radius, seed):
 
 
 @pytest.mark.parametrize("mode", [FRACTION, FULL])
-def test_config2_sampled(mode):
-    _sampled(scenes.config2, mode, 400, 600, 120.0, 2)
+def test_city2km_billboard_sampled(mode):
+    _sampled(scenes.city2km_billboard, mode, 400, 600, 120.0, 2)
 
 
 @pytest.mark.parametrize("mode", [FRACTION, FULL])
-def test_config3_sampled(mode):
-    _sampled(scenes.config3, mode, 300, 500, 150.0, 3)
+def test_city4km_cube_sampled(mode):
+    _sampled(scenes.city4km_cube, mode, 300, 500, 150.0, 3)
 
 
-def test_config2_full_vs_fraction_consistent():
+def test_city2km_full_vs_fraction_consistent():
     """Properties at full size: FULL count is N(q) or 0 and equals N(q) exactly
     where the FRACTION count is N(q); colours are 0 where counts are 0."""
-    scene, q = scenes.config2()
+    scene, q = scenes.city2km_billboard()
     gf = _gpu_map(scene, _with(q, mode=FULL))
     gr = _gpu_map(scene, _with(q, mode=FRACTION))
     full = gf["count"].astype(int)
@@ -152,7 +152,7 @@ def test_config2_full_vs_fraction_consistent():
 def test_recheck_everything_matches_default_and_no_disagreement():
     """Every ray test settled by the exact float64 predicate gives the same map,
     and no float32 decision outside the margin disagreed with it."""
-    scene, q = scenes.config2()
+    scene, q = scenes.city2km_billboard()
     q = Query(q.target, Grid((800.0, 800.0, 0.0), (400.0, 400.0, 150.0), (64, 64, 32)),
               Params(n_bins=16, mode=FRACTION))
     a = _gpu_map(scene, q, stats=True)
@@ -168,7 +168,7 @@ def test_recheck_everything_matches_default_and_no_disagreement():
 
 
 def test_invalid_queries_rejected():
-    scene, q = scenes.config1()
+    scene, q = scenes.plain2d_50rects()
     idx = vcm.vcm_build_index(scene)
     bad = [
         _with(q, n_bins=1),

@@ -80,8 +80,8 @@ def compare_pruned(gpu, orc, scene, query, vp, method):
 @pytest.mark.parametrize("method", [1, 2, 3])
 @pytest.mark.parametrize("mode", [FULL, FRACTION])
 @pytest.mark.parametrize("theta", [1, 3])
-def test_config1_full_map(method, mode, theta):
-    scene, q = scenes.config1()
+def test_plain2d_full_map(method, mode, theta):
+    scene, q = scenes.plain2d_50rects()
     q = _with(q, method=method, mode=mode, theta_blocks=theta, bin_scale=BIN_LOG)
     g = _gpu_map(scene, q)
     vp = np.arange(q.grid.count, dtype=np.int64)
@@ -111,8 +111,8 @@ def test_small_3d_full_map(method, kind):
 
 
 @pytest.mark.parametrize("method", [1, 2, 3])
-def test_config3_sampled(method):
-    scene, q = scenes.config3()
+def test_city4km_cube_sampled(method):
+    scene, q = scenes.city4km_cube()
     q = _with(q, method=method, mode=FULL)
     g = _gpu_map(scene, q)
     rng = np.random.default_rng(7)
@@ -133,7 +133,7 @@ def test_config3_sampled(method):
 
 def test_pruned_gate_matches_brute_map():
     """theta = 1: the pruned methods' visibility gate is the brute force's."""
-    scene, q = scenes.config2()
+    scene, q = scenes.city2km_billboard()
     q = _with(q, mode=FRACTION)
     b = _gpu_map(scene, q)
     for m in (1, 2, 3):
@@ -145,7 +145,7 @@ def test_map_error_matches_oracle():
     """Sec. V-A error of the M and T maps against the E map, reduced on the
     device, equals the oracle's float64 sums over the same colours."""
     import torch
-    scene, q = scenes.config1()
+    scene, q = scenes.plain2d_50rects()
     maps = {m: _gpu_map(scene, _with(q, method=m, mode=FULL)) for m in (1, 2, 3)}
     for m in (2, 3):
         ce = torch.from_numpy(maps[1]["c"]).cuda()

@@ -19,7 +19,7 @@ def _gpu():
 
 @pytest.mark.parametrize("mode", [scenes.FULL, scenes.FRACTION])
 def test_map_independent_of_cell_size(mode):
-    scene, q = scenes.config2()
+    scene, q = scenes.city2km_billboard()
     q = scenes.Query(q.target, q.grid, scenes.Params(**{**q.params.__dict__, "mode": mode}))
     maps = []
     for cs in (8.0, 32.0, 128.0, 512.0):

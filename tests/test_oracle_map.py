@@ -50,7 +50,7 @@ def _samples_independent(t, q):
 
 
 def test_empty_scene_all_visible():
-    s, q = scenes.config1()
+    s, q = scenes.plain2d_50rects()
     o = oracle.vcm_eval(_empty(2), q)
     assert np.all(o["count"] == 32) and np.all(o["nlive"] == 32)
     pts = oracle.viewpoint_coords(q.grid, np.arange(q.grid.count))
@@ -166,9 +166,9 @@ def test_exhaustive_tiny_scenes_against_independent_counts(seed):
     assert blocked > 0 and clear > 0 and (partial > 0 or seed >= 4)
 
 
-def test_mirror_symmetry_config1():
+def test_mirror_symmetry_plain2d():
     """Mirroring scene, target and grid about x = 500 mirrors the map."""
-    s, q = scenes.config1()
+    s, q = scenes.plain2d_50rects()
     q.params.mode = FRACTION
     o = oracle.vcm_eval(s, q)
     lo = s.lo.copy()
@@ -185,7 +185,7 @@ def test_mirror_symmetry_config1():
 
 
 def test_translation_invariance():
-    s, q = scenes.config1()
+    s, q = scenes.plain2d_50rects()
     q.params.mode = FRACTION
     o = oracle.vcm_eval(s, q)
     off = np.array([[1234.5], [-640.25], [0.0]])
@@ -200,11 +200,11 @@ def test_translation_invariance():
 
 
 def test_rejects_invalid():
-    s, q = scenes.config1()
+    s, q = scenes.plain2d_50rects()
     q.grid.origin = (0.1, 0.0, 0.0)
     with pytest.raises(ValueError):
         oracle.vcm_eval(s, q)
-    s, q = scenes.config1()
+    s, q = scenes.plain2d_50rects()
     q.params.n_bins = 1
     with pytest.raises(ValueError):
         oracle.vcm_eval(s, q)

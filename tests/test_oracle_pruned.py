@@ -162,7 +162,7 @@ def test_block_representative():
 
 
 def test_pruned_gate_equals_brute_at_theta_one():
-    scene, q = scenes.config1()
+    scene, q = scenes.plain2d_50rects()
     for mode in (FULL, FRACTION):
         q.params.mode = mode
         b = oracle.vcm_eval(scene, q)
