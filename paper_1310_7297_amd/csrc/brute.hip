@@ -8,9 +8,10 @@
 //   * the wavefront walks, column by column, the corridor swept by the rays
 //     (the convex hull of q and the target's footprint), starting at the
 //     target end where occluders are most likely;
-//   * inside a column, box records are read with wave-uniform (scalar)
-//     loads, so one read serves 64 * NS rays, and the list stops at the first
-//     box whose top lies below the corridor's lowest point;
+//   * inside a column, the lanes read and cull 64 box records at a time
+//     (integer compares), and the list stops at the first box whose top lies
+//     below the corridor's lowest point; each candidate box is then tested
+//     against all 64 * NS rays;
 //   * each lane runs a float32 slab test per ray; a result within `eps` of
 //     the decision boundary is settled by the exact float64 predicate;
 //   * visibility is reduced with wave ballots and popcounts (integers only).
@@ -255,7 +256,8 @@ struct WaveStats {
 __device__ inline unsigned ord(float x) { return x > 0.0f ? __float_as_uint(x) : 0u; }
 
 // The index is immutable while kernels run: read it through the constant
-// address space, so that wave-uniform reads become scalar loads.
+// address space, so that wave-uniform reads (column offsets, the blocker
+// cache's record) become scalar loads.
 // (The host pass of the compiler only needs the declarations.)
 #if defined(__HIP_DEVICE_COMPILE__)
 #define VCM_CONST __attribute__((address_space(4)))
@@ -269,18 +271,15 @@ typedef const VCM_CONST BoxRec *cptr_rec;
 // margin is settled by the exact predicate) and clear the rays it blocks.
 // Returns 0 when the viewpoint is decided (FULL mode: some ray is blocked;
 // FRACTION mode: no ray is left open), else a non-zero mask.
+//
+// blq and bhq are the box's corners minus q (exact: dyadic coordinates).
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
-__device__ __attribute__((always_inline)) inline unsigned long long box_blocks(
-    const BoxRec &B, const TargetDesc &T, const ParamDesc &P, const float *q, unsigned faces,
-    const void *tab, const float (&iv)[NS][3], const int (&sidx)[NS], unsigned long long (&open)[NS],
-    const unsigned long long (&zmask)[NS], WaveStats &ws, unsigned long long &n_disagree) {
+__device__ __attribute__((always_inline)) inline unsigned long long box_test(
+    const float (&blq)[3], const float (&bhq)[3], const TargetDesc &T, const ParamDesc &P, const float *q,
+    unsigned faces, const void *tab, const float (&iv)[NS][3], const int (&sidx)[NS],
+    unsigned long long (&open)[NS], const unsigned long long (&zmask)[NS], WaveStats &ws,
+    unsigned long long &n_disagree) {
     const int lane = threadIdx.x & 63;
-    float blq[3], bhq[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        blq[k] = B.lo[k] - q[k];
-        bhq[k] = B.hi[k] - q[k];
-    }
     unsigned long long open_any = 0;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
@@ -332,6 +331,21 @@ __device__ __attribute__((always_inline)) inline unsigned long long box_blocks(
         open_any |= open[j];
     }
     return MODE == VCM_FULL ? ~0ull : open_any;
+}
+
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
+__device__ __attribute__((always_inline)) inline unsigned long long box_blocks(
+    const BoxRec &B, const TargetDesc &T, const ParamDesc &P, const float *q, unsigned faces,
+    const void *tab, const float (&iv)[NS][3], const int (&sidx)[NS], unsigned long long (&open)[NS],
+    const unsigned long long (&zmask)[NS], WaveStats &ws, unsigned long long &n_disagree) {
+    float blq[3], bhq[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        blq[k] = B.lo[k] - q[k];
+        bhq[k] = B.hi[k] - q[k];
+    }
+    return box_test<DIM, NS, EXACT64, MODE, STATS, TAB>(blq, bhq, T, P, q, faces, tab, iv, sidx, open, zmask,
+                                                       ws, n_disagree);
 }
 
 // The corridor walk of one viewpoint (wave-uniform) along major axis AX:
@@ -415,34 +429,49 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
             for (int ib = ib0; ib <= ib1; ++ib) {
                 const int col = AX == 0 ? ia + X.nx * ib : ib + X.nx * ia;
                 if (STATS) ++ws.cols;
-                // The list ends with a sentinel whose top is below every
-                // floor.  One loop exit, at the bottom: the scalar unit runs
-                // every record through the same few instructions.
-                const VCM_CONST BoxRec *rp = recs + col_start[col];
-                bool more;
-                do {
-                    const BoxRec B = *rp++;
-                    // Every coordinate of the index frame is a non-negative
-                    // float below 2^31 as an integer, so a signed difference
-                    // of two of them has the sign of their comparison.
-                    // Below the corridor's lowest point (so is the rest of
-                    // the list, and so is the sentinel): done with this
-                    // column.  (2-D boxes have an infinite top.)
-                    const bool low = static_cast<int>(__float_as_uint(B.hi[2]) - uzf) < 0;
-                    // Beside the slice, or above its ceiling: cannot meet its rays.
-                    const int side = static_cast<int>(__float_as_uint(B.hi[BX]) - ub0) |
-                                     static_cast<int>(ub1 - __float_as_uint(B.lo[BX])) |
-                                     (DIM == 3 ? static_cast<int>(uzc - __float_as_uint(B.lo[2])) : 0);
-                    more = !low;
-                    if (!low && side >= 0) {
-                        const unsigned long long rest = box_blocks<DIM, NS, EXACT64, MODE, STATS, TAB>(
-                            B, T, P, q, faces, tab, iv, sidx, open, zmask, ws, n_disagree);
-                        if (rest == 0) {
-                            if (MODE == VCM_FULL) blk = static_cast<int>(rp - recs) - 1;
-                            return;
+                // The column's records, 64 at a time, lane l holding record
+                // base + l (the sentinel past the list's end: its top is below
+                // every floor).  Every coordinate of the index frame is a
+                // non-negative float below 2^31 as an integer, so a signed
+                // difference of two of them has the sign of their comparison.
+                const int cb = col_start[col], ce = col_start[col + 1] - 1;
+                for (int base = cb;; base += 64) {
+                    const BoxRec R = recs[min(base + lane, ce)];
+                    // not below the corridor's lowest point (the list is
+                    // sorted by decreasing top; 2-D boxes have an infinite top)
+                    const bool above = static_cast<int>(__float_as_uint(R.hi[2]) - uzf) >= 0;
+                    // and neither beside the slice nor above its ceiling
+                    const int side = static_cast<int>(__float_as_uint(R.hi[BX]) - ub0) |
+                                     static_cast<int>(ub1 - __float_as_uint(R.lo[BX])) |
+                                     (DIM == 3 ? static_cast<int>(uzc - __float_as_uint(R.lo[2])) : 0);
+                    unsigned long long cand = __ballot(above && side >= 0);
+                    const unsigned long long below = __ballot(!above);
+                    if (cand) {
+                        float dl[3], dh[3];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            dl[k] = R.lo[k] - q[k];
+                            dh[k] = R.hi[k] - q[k];
                         }
+                        do {
+                            const int r = __builtin_ctzll(cand);
+                            cand &= cand - 1;
+                            float blq[3], bhq[3];
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) {
+                                blq[k] = readlane_f(dl[k], r);
+                                bhq[k] = readlane_f(dh[k], r);
+                            }
+                            const unsigned long long rest = box_test<DIM, NS, EXACT64, MODE, STATS, TAB>(
+                                blq, bhq, T, P, q, faces, tab, iv, sidx, open, zmask, ws, n_disagree);
+                            if (rest == 0) {
+                                if (MODE == VCM_FULL) blk = base + r;
+                                return;
+                            }
+                        } while (cand);
                     }
-                } while (more);
+                    if (below) break;
+                }
                 // FRACTION mode: pack the unresolved rays into fewer slots
                 if (NS > 1 && MODE == VCM_FRACTION) {
                     int tot = 0, used = 0;
@@ -482,10 +511,11 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
 // Visibility of the live samples from q for one wavefront.  Returns the
 // number of unblocked live samples (FULL mode: exact only when it equals N).
 //
-// Box records arrive by scalar loads; the records that cannot meet the
-// corridor (top below its lowest point, or beside its extent along b) are
-// rejected by integer compares on the scalar unit, so only candidates cost
-// vector instructions.
+// A column's box records are read 64 at a time, one per lane, and the
+// records that cannot meet the corridor (top below its lowest point, beside
+// its extent along b, or above its ceiling) are rejected by integer compares
+// on the lanes; the candidates are then tested one by one against every ray
+// of the wave, their corners handed over by lane reads.
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
 __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     const BruteArgs &A, cptr_i32 col_start, cptr_rec recs, const float *q, unsigned faces,
@@ -498,7 +528,7 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
 
     // ---- a viewpoint inside (or on) an obstacle sees nothing.  Boxes of the
     // index frame have no negative coordinate, so the scan of q's column
-    // compares ordered bit patterns on the scalar unit; the column's list
+    // compares ordered bit patterns, 64 records at a time; the column's list
     // ends with a sentinel (top -inf, lower corner +inf).
     if (q[0] >= 0.0f && q[1] >= 0.0f && q[2] >= 0.0f) {
         const int cx = static_cast<int>(floorf(q[0] * X.inv_cs));
@@ -507,20 +537,21 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
             const unsigned u0 = __builtin_amdgcn_readfirstlane(ord(q[0]));
             const unsigned u1 = __builtin_amdgcn_readfirstlane(ord(q[1]));
             const unsigned u2 = __builtin_amdgcn_readfirstlane(ord(q[2]));
-            const VCM_CONST BoxRec *rp = recs + col_start[cx + X.nx * cy];
-            for (;; ++rp) {
-                const BoxRec B = *rp;
-                // lower than q (so is the rest of the list, and the sentinel)
-                if (static_cast<int>(__float_as_uint(B.hi[2]) - u2) < 0) break;
-                const int out = static_cast<int>(u0 - __float_as_uint(B.lo[0])) |
-                                static_cast<int>(__float_as_uint(B.hi[0]) - u0) |
-                                static_cast<int>(u1 - __float_as_uint(B.lo[1])) |
-                                static_cast<int>(__float_as_uint(B.hi[1]) - u1) |
-                                (DIM == 3 ? static_cast<int>(u2 - __float_as_uint(B.lo[2])) : 0);
-                if (out >= 0) {
+            const int cb = col_start[cx + X.nx * cy], ce = col_start[cx + X.nx * cy + 1] - 1;
+            for (int base = cb;; base += 64) {
+                const BoxRec R = recs[min(base + lane, ce)];
+                // not lower than q (the list is sorted by decreasing top)
+                const bool above = static_cast<int>(__float_as_uint(R.hi[2]) - u2) >= 0;
+                const int out = static_cast<int>(u0 - __float_as_uint(R.lo[0])) |
+                                static_cast<int>(__float_as_uint(R.hi[0]) - u0) |
+                                static_cast<int>(u1 - __float_as_uint(R.lo[1])) |
+                                static_cast<int>(__float_as_uint(R.hi[1]) - u1) |
+                                (DIM == 3 ? static_cast<int>(u2 - __float_as_uint(R.lo[2])) : 0);
+                if (__ballot(above && out >= 0)) {
                     if (STATS) ++ws.inside;
                     return 0;
                 }
+                if (__ballot(!above)) break;
             }
         }
     }
