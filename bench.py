@@ -16,10 +16,16 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic VALU lane-operations per unit of work:
-# one float32 slab test of a ray against a box, and one corridor column visit.
+# Algorithmic lane-operations per unit of work: one float32 slab test of a ray
+# against a box; one corridor column visit; one box record examined by a
+# column scan (its top against the floor, its extent across the walk and its
+# bottom against the slice: four differences, two ors, two compares); one
+# candidate record checked against the corridor over its own extent along the
+# walk (clip, two parameter bounds with margins, four extents, four compares).
 OPS_PER_BOX_TEST = 20
 OPS_PER_COLUMN = 12
+OPS_PER_RECORD = 8
+OPS_PER_NARROW_TEST = 30
 # MI355X: 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz (non-packed lane ops).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_HBM = 8.0e12
@@ -28,8 +34,8 @@ PEAK_HBM = 8.0e12
 # FETCH_SIZE / WRITE_SIZE summary (copy-kernel calibrated), valid only for the
 # kernel sources it was taken on.
 PROFILE = os.path.join(ROOT, "profiles", "k_brute_city20k_cube_fraction.md")
-TRAFFIC_BYTES = 87362790
-TRAFFIC_CELL = 64.0
+TRAFFIC_BYTES = 87633811
+TRAFFIC_CELL = 128.0
 KERNEL_SOURCES = ("brute.hip", "index.hip", "vcm_internal.h")
 
 
@@ -161,7 +167,7 @@ def bench_batch():
     import paper_1310_7297_amd as vcm
     from paper_1310_7297_amd import scenes
     scene, qs = scenes.city6km_batch256()
-    tuning = vcm.vcm_tune_cell_size(scene, qs[::8], cell_min=16.0, cell_max=64.0, reps=1)
+    tuning = vcm.vcm_tune_cell_size(scene, qs[::8], cell_min=16.0, cell_max=128.0, reps=1)
     idx = vcm.vcm_build_index(scene, cell_size=tuning["best_cell"])
     n_vp = sum(q.grid.count for q in qs)
     seq = [vcm.alloc_result(q.grid.count) for q in qs]
@@ -211,7 +217,7 @@ def bench_serve(n_req: int):
     import paper_1310_7297_amd as vcm
     from paper_1310_7297_amd import scenes
     scene, qs = scenes.city8km_serving(n_requests=n_req)
-    tuning = vcm.vcm_tune_cell_size(scene, qs[:32], cell_min=16.0, cell_max=64.0, reps=1)
+    tuning = vcm.vcm_tune_cell_size(scene, qs[:32], cell_min=16.0, cell_max=128.0, reps=1)
     idx = vcm.vcm_build_index(scene, cell_size=tuning["best_cell"])
     res = [vcm.alloc_result(q.grid.count) for q in qs]
     n_vp = sum(q.grid.count for q in qs)
@@ -288,7 +294,7 @@ def main():
     cell = args.cell
     if cell < 0:
         # index autotuner (untimed set-up): fastest column width for this map
-        tuning = vcm.vcm_tune_cell_size(scene, [q], cell_min=32.0, cell_max=128.0, reps=1)
+        tuning = vcm.vcm_tune_cell_size(scene, [q], cell_min=32.0, cell_max=256.0, reps=1)
         cell = tuning["best_cell"]
     t0 = time.perf_counter()
     idx = vcm.vcm_build_index(scene, cell_size=cell)
@@ -307,7 +313,8 @@ def main():
     vps = n_vp * args.steps / wall
     rays_ps = st["rays"] * args.steps / wall
 
-    ops = OPS_PER_BOX_TEST * st["box_tests"] + OPS_PER_COLUMN * st["columns"]
+    ops = (OPS_PER_BOX_TEST * st["box_tests"] + OPS_PER_COLUMN * st["columns"]
+           + OPS_PER_RECORD * st["records"] + OPS_PER_NARROW_TEST * st["narrow_tests"])
     achieved = ops / (kernel_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS,
@@ -315,6 +322,7 @@ def main():
                 "kernel": "k_brute", "kernel_ms": kernel_ms,
                 "box_tests_per_launch": st["box_tests"], "columns_per_launch": st["columns"],
                 "rechecks_per_launch": st["rechecks"],
+                "records_per_launch": st["records"], "narrow_tests_per_launch": st["narrow_tests"],
                 "slot_tests_per_launch": st.get("slot_tests"),
                 "inside_box_viewpoints": st.get("inside_box"),
                 "hbm_bytes_algorithmic": 7 * n_vp,

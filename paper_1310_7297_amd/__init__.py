@@ -87,7 +87,8 @@ class vcm_stats(ctypes.Structure):
                 ("box_tests", ctypes.c_uint64), ("rechecks", ctypes.c_uint64),
                 ("fp32_disagree", ctypes.c_uint64), ("columns", ctypes.c_uint64),
                 ("slot_tests", ctypes.c_uint64), ("inside_box", ctypes.c_uint64),
-                ("t_fallbacks", ctypes.c_uint64), ("kernel_ms", ctypes.c_double)]
+                ("t_fallbacks", ctypes.c_uint64), ("records", ctypes.c_uint64),
+                ("narrow_tests", ctypes.c_uint64), ("kernel_ms", ctypes.c_double)]
 
 
 class vcm_result(ctypes.Structure):

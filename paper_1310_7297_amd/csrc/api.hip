@@ -332,6 +332,8 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     stats->slot_tests = h.slot_tests;
     stats->inside_box = h.inside_box;
     stats->t_fallbacks = h.t_fallbacks;
+    stats->records = h.records;
+    stats->narrow_tests = h.narrow_tests;
     stats->kernel_ms = ms;
     return VCM_OK;
 }

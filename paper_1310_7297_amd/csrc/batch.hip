@@ -363,6 +363,8 @@ vcm_status fill_stats(const DevStats &h, uint64_t viewpoints, float ms, vcm_stat
     stats->slot_tests = h.slot_tests;
     stats->inside_box = h.inside_box;
     stats->t_fallbacks = h.t_fallbacks;
+    stats->records = h.records;
+    stats->narrow_tests = h.narrow_tests;
     stats->kernel_ms = ms;
     return VCM_OK;
 }

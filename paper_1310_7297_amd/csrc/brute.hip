@@ -248,8 +248,16 @@ __device__ inline float slab_gap(const float *inv, const float *lq, const float 
 }
 
 struct WaveStats {
-    unsigned long long tests = 0, slots = 0, rechecks = 0, cols = 0, rays = 0, inside = 0;
+    unsigned long long tests = 0, slots = 0, rechecks = 0, cols = 0, rays = 0, inside = 0, recs = 0, narrow = 0;
 };
+
+// FRACTION-mode compaction buffer of a wavefront, one entry per ray: with up
+// to three slots an entry carries the ray's reciprocal direction beside its
+// sample index, so a moved ray needs no new set-up; with more slots it holds
+// the index alone (an entry of 16 bytes per ray would cut those kernels'
+// occupancy) and the ray is set up again.
+template <int NS>
+using RaySlot = typename std::conditional<(NS <= 3), float4, int>::type;
 
 // A non-negative float as an unsigned integer with the same order; negative
 // values (and -0) map to 0, below every box coordinate of the index frame.
@@ -354,7 +362,7 @@ __device__ __attribute__((always_inline)) inline unsigned long long box_blocks(
 // the boxes met block; returns early when the viewpoint is decided.
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB, int AX>
 __device__ __attribute__((always_inline)) inline void corridor_walk(
-    const BruteArgs &A, cptr_rec recs, cptr_i32 col_start, const float *q, unsigned faces, int *lds,
+    const BruteArgs &A, cptr_rec recs, cptr_i32 col_start, const float *q, unsigned faces, RaySlot<NS> *lds,
     const void *tab, int &blk, float (&iv)[NS][3], int (&sidx)[NS], unsigned long long (&open)[NS],
     unsigned long long (&zmask)[NS], WaveStats &ws, unsigned long long &n_disagree) {
     const TargetDesc &T = A.tgt;
@@ -426,6 +434,7 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
             const unsigned ub1 = __builtin_amdgcn_readlane(ub1_l, sl);
             const unsigned uzf = __builtin_amdgcn_readlane(zf_l, sl);
             const unsigned uzc = __builtin_amdgcn_readlane(zc_l, sl);
+            const float A0s = ia * X.cs, A1s = A0s + X.cs;
             for (int ib = ib0; ib <= ib1; ++ib) {
                 const int col = AX == 0 ? ia + X.nx * ib : ib + X.nx * ia;
                 if (STATS) ++ws.cols;
@@ -446,6 +455,39 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
                                      (DIM == 3 ? static_cast<int>(uzc - __float_as_uint(R.lo[2])) : 0);
                     unsigned long long cand = __ballot(above && side >= 0);
                     const unsigned long long below = __ballot(!above);
+                    // the records up to the first one below the floor
+                    if (STATS) ws.recs += __popcll(__ballot(above)) + (below ? 1 : 0);
+                    if (MODE == VCM_FRACTION && cand) {
+                        if (STATS) ws.narrow += __popcll(cand);
+                        // Narrower: the corridor over only the part of the
+                        // slab that the box spans along a (the slab's bounds
+                        // over a shorter interval).  The rays can meet the
+                        // box only there, and a box that misses the slab is
+                        // listed in the columns where it lies.  FRACTION mode
+                        // only: there every candidate costs a test of every
+                        // open ray, while FULL mode ends a viewpoint at its
+                        // first blocked ray and the extra bounds cost more
+                        // than they save.
+                        const float ca0 = fmaxf(R.lo[AX], A0s), ca1 = fminf(R.hi[AX], A1s);
+                        const float s1 = ca1 - qa, s2 = ca0 - qa;
+                        float m0 = 0.0f, m1 = 1.0f;
+                        bool tight = ca0 <= ca1;
+                        if (ua0 > 0.0f) m1 = fminf(m1, s1 * iua0);
+                        else if (ua0 < 0.0f) m0 = fmaxf(m0, s1 * iua0);
+                        else tight = tight && s1 >= 0.0f;
+                        if (ua1 > 0.0f) m0 = fmaxf(m0, s2 * iua1);
+                        else if (ua1 < 0.0f) m1 = fminf(m1, s2 * iua1);
+                        else tight = tight && s2 <= 0.0f;
+                        m0 = fmaxf(0.0f, m0 - kLambdaMargin);
+                        m1 = fminf(1.0f, m1 + kLambdaMargin);
+                        tight = tight && m0 <= m1;
+                        tight = tight && R.hi[BX] >= fminf(qb + m0 * vb0, qb + m1 * vb0) - kWalkMargin &&
+                                R.lo[BX] <= fmaxf(qb + m0 * vb1, qb + m1 * vb1) + kWalkMargin;
+                        if (DIM == 3)
+                            tight = tight && R.hi[2] >= fminf(qz + m0 * wz0, qz + m1 * wz0) - kWalkMargin &&
+                                    R.lo[2] <= fmaxf(qz + m0 * wz1, qz + m1 * wz1) + kWalkMargin;
+                        cand &= __ballot(tight);
+                    }
                     if (cand) {
                         float dl[3], dh[3];
 #pragma unroll
@@ -484,7 +526,13 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
                         int pos = 0;
 #pragma unroll
                         for (int j = 0; j < NS; ++j) {
-                            if ((open[j] >> lane) & 1) lds[pos + mbcnt(open[j])] = sidx[j];
+                            if ((open[j] >> lane) & 1) {
+                                if constexpr (NS <= 3)
+                                    lds[pos + mbcnt(open[j])] =
+                                        make_float4(iv[j][0], iv[j][1], iv[j][2], __int_as_float(sidx[j]));
+                                else
+                                    lds[pos + mbcnt(open[j])] = sidx[j];
+                            }
                             pos += __popcll(open[j]);
                         }
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -493,9 +541,21 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
 #pragma unroll
                         for (int j = 0; j < NS; ++j) {
                             const bool live = j * 64 + lane < tot;
-                            sidx[j] = live ? lds[j * 64 + lane] : 0;
-                            float sp[3];
-                            const bool zl = ray_setup<DIM, TAB>(T, faces, q, sidx[j], sp, iv[j], tab);
+                            bool zl = false;
+                            if constexpr (NS <= 3) {
+                                const float4 r = lds[live ? j * 64 + lane : 0];
+                                sidx[j] = __float_as_int(r.w);
+                                iv[j][0] = r.x;
+                                iv[j][1] = r.y;
+                                iv[j][2] = r.z;
+                                // a zero direction component has reciprocal 0
+#pragma unroll
+                                for (int k = 0; k < DIM; ++k) zl = zl || iv[j][k] == 0.0f;
+                            } else {
+                                sidx[j] = live ? lds[j * 64 + lane] : 0;
+                                float sp[3];
+                                zl = ray_setup<DIM, TAB>(T, faces, q, sidx[j], sp, iv[j], tab);
+                            }
                             open[j] = __ballot(live);
                             zmask[j] = __ballot(zl) & open[j];
                         }
@@ -519,7 +579,7 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
 __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     const BruteArgs &A, cptr_i32 col_start, cptr_rec recs, const float *q, unsigned faces,
-    int N, int *lds, const void *tab, int &blk, WaveStats &ws,
+    int N, RaySlot<NS> *lds, const void *tab, int &blk, WaveStats &ws,
     unsigned long long &n_disagree) {
     const TargetDesc &T = A.tgt;
     const ParamDesc &P = A.prm;
@@ -547,11 +607,13 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
                                 static_cast<int>(u1 - __float_as_uint(R.lo[1])) |
                                 static_cast<int>(__float_as_uint(R.hi[1]) - u1) |
                                 (DIM == 3 ? static_cast<int>(u2 - __float_as_uint(R.lo[2])) : 0);
+                const unsigned long long below = __ballot(!above);
+                if (STATS) ws.recs += __popcll(__ballot(above)) + (below ? 1 : 0);
                 if (__ballot(above && out >= 0)) {
                     if (STATS) ++ws.inside;
                     return 0;
                 }
-                if (__ballot(!above)) break;
+                if (below) break;
             }
         }
     }
@@ -640,7 +702,7 @@ struct Dispenser {
 // lanes at once.  `item` counts from the start of the query's items.
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
 __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &A, cptr_i32 col_start,
-                                                               cptr_rec recs, unsigned item, int *lds,
+                                                               cptr_rec recs, unsigned item, RaySlot<NS> *lds,
                                                                const void *tab, WaveStats &ws,
                                                                unsigned long long &n_disagree) {
     using R = typename std::conditional<EXACT64, double, float>::type;
@@ -655,10 +717,9 @@ __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &
     const int jj = row % n1, kk = A.k_begin + row / n1;
     const int nv = min(chunk, n0 - x0);
     const int64_t v0 = x0 + static_cast<int64_t>(n0) * (jj + static_cast<int64_t>(n1) * kk);
-    uint8_t o_bin = 0;
-    float o_c = 0.0f;
-    uint16_t o_cnt = 0;
-    uint32_t o_gate = 0;
+    // lane t keeps the counts of viewpoint t of the item
+    int o_cnt = 0, o_n = 0;
+    bool o_fov = false;
     int blk = -1;  // record of the last blocking box (FULL mode)
     for (int t = 0; t < nv; ++t) {
         // grid index; in gate mode the launch grid is the block grid and
@@ -697,40 +758,46 @@ __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &
         const int N = nf * T.per_facet;
         const bool fov = in_fov<DIM>(T, P, q);
         int cnt = 0;
-        R col = R(0);
         if (fov && N > 0) {
             if (STATS) ws.rays += N;
             const int vis = trace_viewpoint<DIM, NS, EXACT64, MODE, STATS, TAB>(
                 A, col_start, recs, q, faces, N, lds, tab, blk, ws, n_disagree);
-            if (MODE == VCM_FRACTION) {
-                cnt = vis;
-                if (vis > 0) col = (R(vis) / R(N)) * raw_colour<DIM, R>(T, P, q);
-            } else if (vis == N) {
-                cnt = N;
-                col = raw_colour<DIM, R>(T, P, q);
-            }
+            // FRACTION mode: the visible samples; FULL mode: N when all are
+            cnt = MODE == VCM_FRACTION ? vis : (vis == N ? N : 0);
         }
-        R cb = col;
-        if (P.bin_scale == VCM_BIN_LOG) {
-            const R veff = col * R(P.V0);
-            cb = veff <= R(P.mu) ? R(0) : fmin(R(1), log(veff / R(P.mu)) * R(P.inv_log_V0_mu));
-        }
-        const int bn = min(P.n_bins - 1, static_cast<int>(floor(cb * R(P.n_bins))));
         if (lane == t) {
-            o_bin = static_cast<uint8_t>(bn);
-            o_c = static_cast<float>(col);
-            o_cnt = static_cast<uint16_t>(cnt);
-            o_gate = static_cast<uint32_t>(cnt) | (static_cast<uint32_t>(N) << 10) |
-                     (fov ? (1u << 20) : 0u);
+            o_cnt = cnt;
+            o_n = N;
+            o_fov = fov;
         }
     }
     if (lane < nv) {
         if (A.gate) {
-            A.gate[v0 + lane] = o_gate;
+            A.gate[v0 + lane] = static_cast<uint32_t>(o_cnt) | (static_cast<uint32_t>(o_n) << 10) |
+                                (o_fov ? (1u << 20) : 0u);
         } else {
-            A.bin[v0 + lane] = o_bin;
-            if (A.c) A.c[v0 + lane] = o_c;
-            if (A.count) A.count[v0 + lane] = o_cnt;
+            // measure and bin, one lane per viewpoint of the item (the lane
+            // computes its viewpoint's position exactly as the walk did)
+            float q[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int ik = k == 0 ? x0 + lane : (k == 1 ? jj : kk);
+                q[k] = (k < DIM) ? A.grid.o[k] + static_cast<float>(2 * ik + 1) * A.grid.h2[k] : 0.0f;
+            }
+            R col = R(0);
+            if (o_cnt > 0) {
+                col = raw_colour<DIM, R>(T, P, q);
+                if (MODE == VCM_FRACTION) col = (R(o_cnt) / R(o_n)) * col;
+            }
+            R cb = col;
+            if (P.bin_scale == VCM_BIN_LOG) {
+                const R veff = col * R(P.V0);
+                cb = veff <= R(P.mu) ? R(0) : fmin(R(1), log(veff / R(P.mu)) * R(P.inv_log_V0_mu));
+            }
+            const int bn = min(P.n_bins - 1, static_cast<int>(floor(cb * R(P.n_bins))));
+            A.bin[v0 + lane] = static_cast<uint8_t>(bn);
+            if (A.c) A.c[v0 + lane] = static_cast<float>(col);
+            if (A.count) A.count[v0 + lane] = static_cast<uint16_t>(o_cnt);
         }
     }
 }
@@ -745,6 +812,8 @@ __device__ inline void flush_stats(DevStats *st, const WaveStats &ws, unsigned l
         atomicAdd(&st->rechecks, ws.rechecks);
         atomicAdd(&st->columns, ws.cols);
         atomicAdd(&st->inside_box, ws.inside);
+        atomicAdd(&st->records, ws.recs);
+        atomicAdd(&st->narrow_tests, ws.narrow);
     }
     if (n_disagree) atomicAdd(&st->fp32_disagree, n_disagree);  // per lane
 }
@@ -763,11 +832,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE
     // same kernel symbol in both compiler passes; constant-space view inside
     const cptr_i32 col_start = (cptr_i32)col_start_g;
     const cptr_rec recs = (cptr_rec)recs_g;
-    __shared__ int lds_rays[4][kMaxSamples];
+    __shared__ RaySlot<NS> lds_rays[4][NS * 64];
     __shared__ float4 s_tab[kTableMax];
     build_sample_table<DIM>(A.tgt, s_tab);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int *lds = lds_rays[wave];
+    RaySlot<NS> *lds = lds_rays[wave];
     WaveStats ws;
     unsigned long long n_disagree = 0;
     Dispenser D;
@@ -794,11 +863,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE
     const cptr_rec recs = (cptr_rec)recs_g;
     const VCM_CONST BruteArgs *qs = (const VCM_CONST BruteArgs *)qs_g;
     const VCM_CONST uint32_t *group_end = (const VCM_CONST uint32_t *)group_end_g;
-    __shared__ int lds_rays[4][kMaxSamples];
+    __shared__ RaySlot<NS> lds_rays[4][NS * 64];
     __shared__ float4 s_tab[kTableMax];
     __shared__ unsigned s_group;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int *lds = lds_rays[wave];
+    RaySlot<NS> *lds = lds_rays[wave];
     int cur_q = -1;  // query whose samples the table holds (workgroup-uniform)
     WaveStats ws;
     unsigned long long n_disagree = 0;

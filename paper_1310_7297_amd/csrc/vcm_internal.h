@@ -107,6 +107,8 @@ struct DevStats {
     unsigned long long slot_tests;
     unsigned long long inside_box;
     unsigned long long t_fallbacks;
+    unsigned long long records;
+    unsigned long long narrow_tests;
 };
 
 // Everything one brute-force launch needs (passed by value).
