@@ -275,85 +275,82 @@ __device__ inline unsigned ord(float x) { return x > 0.0f ? __float_as_uint(x) :
 typedef const VCM_CONST int32_t *cptr_i32;
 typedef const VCM_CONST BoxRec *cptr_rec;
 
-// Test the open rays against one box B (slot by slot; a result within the
-// margin is settled by the exact predicate) and clear the rays it blocks.
-// Returns 0 when the viewpoint is decided (FULL mode: some ray is blocked;
-// FRACTION mode: no ray is left open), else a non-zero mask.
-//
-// blq and bhq are the box's corners minus q (exact: dyadic coordinates).
+// Rays of slot j (among the open ones) that a box blocks: float32 slab test
+// with margin eps; results inside the margin, and rays with a zero direction
+// component, are settled by the exact predicate.  blq and bhq are the box's
+// corners minus q (exact: dyadic coordinates).
+template <int DIM, int NS, bool EXACT64, bool STATS, int TAB>
+__device__ __attribute__((always_inline)) inline unsigned long long slot_hits(
+    int j, const float (&blq)[3], const float (&bhq)[3], const TargetDesc &T, const ParamDesc &P,
+    const float *q, unsigned faces, const void *tab, const float (&iv)[NS][3], const int (&sidx)[NS],
+    const unsigned long long (&open)[NS], const unsigned long long (&zmask)[NS], WaveStats &ws,
+    unsigned long long &n_disagree) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long hit, unsure;
+    float gap = 0.0f;
+    if (EXACT64) {
+        hit = 0;
+        unsure = open[j];
+    } else {
+        // eps = +inf sends every test to the exact predicate
+        gap = slab_gap<DIM>(iv[j], blq, bhq);
+        hit = __ballot(gap > P.eps) & open[j];
+        unsure = (__ballot(fabsf(gap) <= P.eps) | zmask[j]) & open[j];
+    }
+    if (__builtin_expect(unsure != 0, 0)) {
+        bool ex = false;
+        if ((unsure >> lane) & 1) {
+            float sp[3], d[3];
+            // opaque copy: keeps this rare work out of the hot loops (it is
+            // loop-invariant per ray)
+            int si = sidx[j];
+            asm volatile("" : "+v"(si));
+            sample_pos<DIM, TAB>(T, faces, si, sp, tab);
+            float lq2[3], hq2[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                d[k] = sp[k] - q[k];
+                // keep this rare path's work inside the branch
+                lq2[k] = blq[k];
+                hq2[k] = bhq[k];
+                asm volatile("" : "+v"(lq2[k]), "+v"(hq2[k]));
+            }
+            ex = exact_contact<DIM>(d, lq2, hq2);
+            if (STATS && !EXACT64 && !((zmask[j] >> lane) & 1) && fabsf(gap) > P.eps_ref &&
+                (gap > 0.0f) != ex)
+                ++n_disagree;
+        }
+        hit = (hit & ~unsure) | (__ballot(ex) & unsure);
+    }
+    if (STATS) {
+        ws.tests += __popcll(open[j]);
+        ws.rechecks += EXACT64 ? 0 : __popcll(unsure);
+        ++ws.slots;
+    }
+    return hit;
+}
+
+// Test the open rays against one box (slot by slot) and clear the rays it
+// blocks.  Returns 0 when the viewpoint is decided (FULL mode: some ray is
+// blocked; FRACTION mode: no ray is left open), else a non-zero mask.
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
 __device__ __attribute__((always_inline)) inline unsigned long long box_test(
     const float (&blq)[3], const float (&bhq)[3], const TargetDesc &T, const ParamDesc &P, const float *q,
     unsigned faces, const void *tab, const float (&iv)[NS][3], const int (&sidx)[NS],
     unsigned long long (&open)[NS], const unsigned long long (&zmask)[NS], WaveStats &ws,
     unsigned long long &n_disagree) {
-    const int lane = threadIdx.x & 63;
     unsigned long long open_any = 0;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         if (!open[j]) continue;
-        unsigned long long hit, unsure;
-        float gap = 0.0f;
-        if (EXACT64) {
-            hit = 0;
-            unsure = open[j];
-        } else {
-            // eps = +inf sends every test to the exact predicate
-            gap = slab_gap<DIM>(iv[j], blq, bhq);
-            hit = __ballot(gap > P.eps) & open[j];
-            unsure = (__ballot(fabsf(gap) <= P.eps) | zmask[j]) & open[j];
-        }
-        if (__builtin_expect(unsure != 0, 0)) {
-            bool ex = false;
-            if ((unsure >> lane) & 1) {
-                float sp[3], d[3];
-                // opaque copy: keeps this rare work out of the hot loops (it is
-                // loop-invariant per ray)
-                int si = sidx[j];
-                asm volatile("" : "+v"(si));
-                sample_pos<DIM, TAB>(T, faces, si, sp, tab);
-                float lq2[3], hq2[3];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    d[k] = sp[k] - q[k];
-                    // keep this rare path's work inside the branch
-                    lq2[k] = blq[k];
-                    hq2[k] = bhq[k];
-                    asm volatile("" : "+v"(lq2[k]), "+v"(hq2[k]));
-                }
-                ex = exact_contact<DIM>(d, lq2, hq2);
-                if (STATS && !EXACT64 && !((zmask[j] >> lane) & 1) && fabsf(gap) > P.eps_ref &&
-                    (gap > 0.0f) != ex)
-                    ++n_disagree;
-            }
-            hit = (hit & ~unsure) | (__ballot(ex) & unsure);
-        }
-        if (STATS) {
-            ws.tests += __popcll(open[j]);
-            ws.rechecks += EXACT64 ? 0 : __popcll(unsure);
-            ++ws.slots;
-        }
+        const unsigned long long hit = slot_hits<DIM, NS, EXACT64, STATS, TAB>(j, blq, bhq, T, P, q, faces, tab, iv,
+                                                                              sidx, open, zmask, ws, n_disagree);
         open[j] &= ~hit;
         // FULL mode: one blocked ray decides the viewpoint
         if (MODE == VCM_FULL && hit != 0) return 0;
         open_any |= open[j];
     }
     return MODE == VCM_FULL ? ~0ull : open_any;
-}
-
-template <int DIM, int NS, bool EXACT64, int MODE, bool STATS, int TAB>
-__device__ __attribute__((always_inline)) inline unsigned long long box_blocks(
-    const BoxRec &B, const TargetDesc &T, const ParamDesc &P, const float *q, unsigned faces,
-    const void *tab, const float (&iv)[NS][3], const int (&sidx)[NS], unsigned long long (&open)[NS],
-    const unsigned long long (&zmask)[NS], WaveStats &ws, unsigned long long &n_disagree) {
-    float blq[3], bhq[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        blq[k] = B.lo[k] - q[k];
-        bhq[k] = B.hi[k] - q[k];
-    }
-    return box_test<DIM, NS, EXACT64, MODE, STATS, TAB>(blq, bhq, T, P, q, faces, tab, iv, sidx, open, zmask,
-                                                       ws, n_disagree);
 }
 
 // The corridor walk of one viewpoint (wave-uniform) along major axis AX:
@@ -623,6 +620,20 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     int sidx[NS];
     unsigned long long open[NS];
     unsigned long long zmask[NS];  // rays with a zero direction component
+    // FULL mode: the box that blocked the previous viewpoint of this work
+    // item usually blocks this one too, and one blocked ray settles the
+    // viewpoint; each slot is tested against it as soon as it is set up, so
+    // a viewpoint settled by an early slot sets up no more rays.
+    float bl[3] = {0.0f, 0.0f, 0.0f}, bh[3] = {0.0f, 0.0f, 0.0f};
+    const bool cached = MODE == VCM_FULL && blk >= 0;
+    if (cached) {
+        const BoxRec B = recs[blk];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            bl[k] = B.lo[k] - q[k];
+            bh[k] = B.hi[k] - q[k];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         sidx[j] = j * 64 + lane;
@@ -631,14 +642,9 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
         const bool zl = ray_setup<DIM, TAB>(T, faces, q, live ? sidx[j] : 0, sp, iv[j], tab);
         open[j] = __ballot(live);
         zmask[j] = __ballot(zl) & open[j];
-    }
-
-    // ---- FULL mode: the box that blocked the previous viewpoint of this
-    // work item usually blocks this one too; one test settles it.
-    if (MODE == VCM_FULL && blk >= 0) {
-        const BoxRec B = recs[blk];
-        if (box_blocks<DIM, NS, EXACT64, MODE, STATS, TAB>(B, T, P, q, faces, tab, iv, sidx, open, zmask, ws,
-                                                           n_disagree) == 0)
+        if (cached && open[j] &&
+            slot_hits<DIM, NS, EXACT64, STATS, TAB>(j, bl, bh, T, P, q, faces, tab, iv, sidx, open, zmask, ws,
+                                                    n_disagree) != 0)
             return 0;
     }
 
