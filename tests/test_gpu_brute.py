@@ -102,6 +102,41 @@ def test_tiny_lattice_scenes(seed, mode):
             compare(gm, o, 16, label=f"tiny seed {seed} fov {fov} cs {cs}")
 
 
+def _column_aligned_city(seed, step=32.0, extent=512.0, n=80):
+    """Boxes whose footprints are whole multiples of `step`, so that their
+    faces lie on the column and slab boundaries of every index width from
+    `step` up; heights on a 2^-2 lattice; none within 2 m of the target."""
+    rng = np.random.default_rng(seed)
+    cells = int(extent / step)
+    lo_xy = rng.integers(0, cells - 1, size=(2, n)).astype(np.float64) * step
+    hi_xy = lo_xy + rng.integers(1, 3, size=(2, n)).astype(np.float64) * step
+    h = np.round(rng.uniform(4.0, 40.0, n) * 4.0) / 4.0
+    lo = np.vstack([lo_xy, np.zeros(n)])
+    hi = np.vstack([hi_xy, h])
+    c, half = np.array([272.0, 272.0, 8.0]), 8.0 + 2.0
+    keep = np.any((lo > (c + half)[:, None]) | (hi < (c - half)[:, None]), axis=0)
+    return Scene(3, lo[:, keep], hi[:, keep])
+
+
+@pytest.mark.parametrize("samples", [(8, 8), (16, 8)])
+@pytest.mark.parametrize("mode", [FRACTION, FULL])
+def test_column_aligned_boxes_every_width(samples, mode):
+    """Box faces and viewpoints on column boundaries, at index widths of 32 to
+    256 m: the corridor bounds, their narrowing to a box's part of a slab
+    (FRACTION mode) and the blocker-first set-up (FULL mode) must lose no
+    blocking box.  8x8 samples per face keep up to 192 rays (three slots),
+    16x8 up to 384 (six slots)."""
+    sc = _column_aligned_city(7)
+    t = Target(CUBE, (272.0, 272.0, 8.0), (16.0, 0.0), samples_u=samples[0], samples_v=samples[1])
+    # viewpoint x and y at multiples of 32 m: on the column boundaries
+    g = Grid((-16.0, -16.0, 0.0), (576.0, 576.0, 128.0), (18, 18, 8))
+    q = Query(t, g, Params(n_bins=16, mode=mode))
+    o = oracle.vcm_eval(sc, q, nthreads=NT)
+    assert (o["count"] > 0).sum() > 100 and (o["count"] == 0).sum() > 100
+    for cs in (32.0, 64.0, 128.0, 256.0):
+        compare(_gpu_map(sc, q, cell_size=cs), o, 16, label=f"aligned {samples} cs {cs}")
+
+
 def test_empty_scene_and_single_viewpoint():
     t = Target(BILLBOARD, (0.0, 0.0, 10.0), (8.0, 4.0), normal_axis=0, samples_u=16, samples_v=8)
     sc = Scene(3, np.zeros((3, 0)), np.zeros((3, 0)))
