@@ -183,9 +183,9 @@ typedef struct {
     uint64_t t_fallbacks;    /* VCM_PRUNED_T: viewpoints no tangent trapezoid
                                 contained (coloured by their exact cell)    */
     uint64_t records;        /* box records the column scans examined        */
-    uint64_t narrow_tests;   /* FRACTION mode: candidate records checked
-                                against the corridor over their own extent
-                                along the walk                              */
+    uint64_t narrow_tests;   /* candidate records checked against the
+                                corridor over their own extent along the
+                                walk                                        */
     double kernel_ms;        /* device time of the call's kernels            */
 } vcm_stats;
 

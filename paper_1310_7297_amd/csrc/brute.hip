@@ -454,17 +454,13 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
                     const unsigned long long below = __ballot(!above);
                     // the records up to the first one below the floor
                     if (STATS) ws.recs += __popcll(__ballot(above)) + (below ? 1 : 0);
-                    if (MODE == VCM_FRACTION && cand) {
+                    if (cand) {
                         if (STATS) ws.narrow += __popcll(cand);
                         // Narrower: the corridor over only the part of the
                         // slab that the box spans along a (the slab's bounds
                         // over a shorter interval).  The rays can meet the
                         // box only there, and a box that misses the slab is
-                        // listed in the columns where it lies.  FRACTION mode
-                        // only: there every candidate costs a test of every
-                        // open ray, while FULL mode ends a viewpoint at its
-                        // first blocked ray and the extra bounds cost more
-                        // than they save.
+                        // listed in the columns where it lies.
                         const float ca0 = fmaxf(R.lo[AX], A0s), ca1 = fminf(R.hi[AX], A1s);
                         const float s1 = ca1 - qa, s2 = ca0 - qa;
                         float m0 = 0.0f, m1 = 1.0f;
