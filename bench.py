@@ -34,7 +34,7 @@ PEAK_HBM = 8.0e12
 # FETCH_SIZE / WRITE_SIZE summary (copy-kernel calibrated), valid only for the
 # kernel sources it was taken on.
 PROFILE = os.path.join(ROOT, "profiles", "k_brute_city20k_cube_fraction.md")
-TRAFFIC_BYTES = 87669727
+TRAFFIC_BYTES = 87600525
 TRAFFIC_CELL = 128.0
 KERNEL_SOURCES = ("brute.hip", "index.hip", "vcm_internal.h")
 

@@ -228,7 +228,7 @@ typedef struct vcm_batch vcm_batch;
 
 typedef struct {
     int32_t chunk;          /* viewpoints per work item, 1..64; 0 = by mode
-                               (FULL 32, FRACTION 8)                         */
+                               (FULL 64, FRACTION 8)                         */
     int32_t blocks_per_cu;  /* persistent workgroups per CU, 1..16; 0 = default 8 */
     int32_t autotune;       /* 1: at creation, time the candidate shapes
                                (chunk 4/8/16/32 x 4/8 workgroups per CU) on a

@@ -150,7 +150,7 @@ struct Tuning {
 // balance better in short runs.
 inline int chunk_for(const Tuning &t, int mode) {
     if (t.chunk > 0) return t.chunk;
-    return mode == VCM_FULL ? 32 : 8;
+    return mode == VCM_FULL ? 64 : 8;
 }
 
 // Host-side index object behind the opaque vcm_index handle.
