@@ -231,7 +231,7 @@ typedef struct {
                                (FULL 64, FRACTION 8)                         */
     int32_t blocks_per_cu;  /* persistent workgroups per CU, 1..16; 0 = default 8 */
     int32_t autotune;       /* 1: at creation, time the candidate shapes
-                               (chunk 4/8/16/32 x 4/8 workgroups per CU) on a
+                               (chunk 4/8/16/32/64 x 4/8 workgroups per CU) on a
                                sample of the queries and keep the fastest;
                                an explicit chunk or blocks_per_cu wins.  This
                                runs the kernels and writes result buffers.  */

@@ -327,7 +327,7 @@ vcm_status autotune(vcm_batch *b, const vcm_query *qs, const vcm_result *rs, int
         hipFree(sub.d_base);
         return set_error(VCM_E_DEVICE, "stream creation failed");
     }
-    static const int kChunks[] = {4, 8, 16, 32};
+    static const int kChunks[] = {4, 8, 16, 32, 64};
     static const int kBlocks[] = {4, 8};
     Tuning best = p.tune;
     float best_ms = 1e30f;

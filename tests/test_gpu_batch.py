@@ -101,7 +101,7 @@ def test_prepared_batch_replays(use_graph):
     b = vcm.Batch(idx, qs, res, autotune=True, use_graph=use_graph, precision=prec)
     info = b.info()
     assert info["graph"] == int(use_graph)
-    assert info["chunk"] in (4, 8, 16, 32) and info["blocks_per_cu"] in (4, 8)
+    assert info["chunk"] in (4, 8, 16, 32, 64) and info["blocks_per_cu"] in (4, 8)
     assert info["viewpoints"] == sum(q.grid.count for q in qs)
     for rep in range(3):
         for r in res:
