@@ -12,7 +12,9 @@ from typing import Dict, Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libvcm_oracle.so")
+# VCM_ORACLE_LIB names another build of the same source (the mutation tests
+# load copies of the oracle with a planted slip this way).
+_LIB_PATH = os.environ.get("VCM_ORACLE_LIB") or os.path.join(_HERE, "libvcm_oracle.so")
 _lib = None
 
 
@@ -215,6 +217,8 @@ def _plib():
         L.vo_map_error.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                    ctypes.c_void_p, ctypes.c_void_p]
         L.vo_error_bounds.argtypes = [ctypes.POINTER(VoCells), ctypes.c_int, ctypes.c_void_p]
+        L.vo_bound_measured.argtypes = [ctypes.POINTER(VoCells), ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
         L._pruned_ready = True
     return L
 
@@ -254,6 +258,16 @@ class Cells:
     def error_bounds(self, dim: int):
         out = np.zeros(2)
         _plib().vo_error_bounds(ctypes.byref(self._c), int(dim), out.ctypes.data)
+        return {"mbr": out[0], "tangent": out[1]}
+
+    def bound_measured(self, D, alpha, A: float):
+        """Sums of |V_M - V_E| A and |V_T - V_E| A (radians times size) over
+        viewpoints with meridian coordinates (D, alpha), each of size A."""
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        out = np.zeros(2)
+        _plib().vo_bound_measured(ctypes.byref(self._c), len(D), D.ctypes.data, alpha.ctypes.data,
+                                  float(A), out.ctypes.data)
         return {"mbr": out[0], "tangent": out[1]}
 
     def __del__(self):

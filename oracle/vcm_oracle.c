@@ -36,8 +36,11 @@
  *     aid that spreads visual angles between mu and V0 over the bins.
  *
  * Every function is pinned by tests against closed forms, invariants, brute
- * force on tiny inputs or the paper's worked example, except the error
- * bounds of Sec. IV-A (vo_error_bounds): parity unpinned beyond their order.
+ * force on tiny inputs or the paper's worked example.  The error bounds of
+ * Sec. IV-A (vo_error_bounds) are pinned only from below: they must exceed
+ * the error measured over the whole region of distinguishable visibility
+ * (vo_bound_measured); the paper prints no value of either bound that could
+ * pin them exactly.
  */
 #include <math.h>
 #include <pthread.h>
@@ -261,7 +264,9 @@ void vo_measure(const vo_target *t, const vo_params *p, const double *q, double 
  * centre and is symmetric about the target normal n (viewer-at-target
  * symmetry, Sec. III-A): angle(q - m, n) <= FOV / 2, closed.  The test
  * compares (Delta.n)^2 with cos^2(FOV/2) |Delta|^2; cos^2 is an exact rational
- * for the table's half-angles 30/60/120/150 degrees. */
+ * for the half-angles 30/45/60/120/135/150 degrees (the table's FOVs and 90 /
+ * 270 degrees), which makes the comparison exact on the 2^-8 lattice: a point
+ * on the wedge's boundary is inside. */
 int vo_in_fov(const vo_target *t, const vo_params *p, const double *q)
 {
     double half = p->fov_deg / 2.0;
@@ -278,6 +283,8 @@ int vo_in_fov(const vo_target *t, const vo_params *p, const double *q)
     double c2;
     if (half == 30.0 || half == 150.0)
         c2 = 0.75;
+    else if (half == 45.0 || half == 135.0)
+        c2 = 0.5;
     else if (half == 60.0 || half == 120.0)
         c2 = 0.25;
     else {
@@ -837,6 +844,26 @@ void vo_map_error(const double *ce, const double *ca, int64_t n, double *signed_
     *abs_err = den > 0 ? ab / den : 0.0;
 }
 
+/* Measured approximation error in the units of the Sec. IV-A bounds.  Each
+ * of the n viewpoints, given by its meridian coordinates (D[k], alpha[k]),
+ * stands for a region of size A (an area in 2-D, a volume in 3-D); the sums
+ * over the viewpoints of |V_M - V_E| A and |V_T - V_E| A are returned in
+ * out[0] and out[1], visual angles in radians (colours times V0). */
+void vo_bound_measured(const vo_cells *c, int64_t n, const double *D, const double *alpha,
+                       double A, double *out)
+{
+    double m = 0.0, t = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        double col[3];
+        int cell[2], tf;
+        vo_pruned_colours(c, D[k], alpha[k], col, cell, &tf);
+        m += fabs(col[1] - col[0]) * c->V0 * A;
+        t += fabs(col[2] - col[0]) * c->V0 * A;
+    }
+    out[0] = m;
+    out[1] = t;
+}
+
 /* Error bounds of Sec. IV-A, evaluated as printed, per ring i with radii
  * r_i = d_i, r_{i+1} = d_{i+1}:
  *   MBR:     dr = sqrt(2) r_{i+1};             bands counted below
@@ -847,7 +874,9 @@ void vo_map_error(const double *ce, const double *ca, int64_t n, double *signed_
  *   dc = n a_i mu, E = sum over the ring's cells of dc * A_cell,
  * A_cell the cell's area in the (rho, h) quadrant (2-D) or its volume of
  * revolution about the normal axis (3-D).  out = {E_MBR, E_Tangent}.
- * Parity unpinned beyond 0 < E_Tangent < E_MBR: the paper prints no value
+ * Pinned only from below (they must exceed the measured error of
+ * vo_bound_measured over the whole region, for one quadrant in 2-D and one
+ * half-space in 3-D) and by 0 < E_Tangent < E_MBR: the paper prints no value
  * of either bound for a scene that can be rebuilt here. */
 void vo_error_bounds(const vo_cells *c, int dim, double *out)
 {

@@ -156,8 +156,11 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
         p->fov_kind = kFovHalf;
     } else {
         p->fov_kind = half_fov < 90.0 ? kFovNarrow : kFovWide;
+        // exact for these half angles: a viewpoint on the wedge's boundary is inside
         if (half_fov == 30.0 || half_fov == 150.0)
             p->fov_c2 = 0.75;
+        else if (half_fov == 45.0 || half_fov == 135.0)
+            p->fov_c2 = 0.5;
         else if (half_fov == 60.0 || half_fov == 120.0)
             p->fov_c2 = 0.25;
         else {

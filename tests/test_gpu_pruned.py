@@ -86,10 +86,11 @@ def test_plain2d_full_map(method, mode, theta):
     g = _gpu_map(scene, q)
     vp = np.arange(q.grid.count, dtype=np.int64)
     o = oracle.vcm_eval_pruned(scene, q, method, theta, vp)
-    compare_pruned(g, o, scene, q, vp, method)
+    ties = compare_pruned(g, o, scene, q, vp, method)
     if method == 3:
-        assert g["stats"]["t_fallbacks"] == int(
-            o["t_fallback"][(o["count"] > 0)].sum()) or True
+        # viewpoints no tangent trapezoid holds, among those that get a colour
+        want = int(o["t_fallback"][(o["count"] > 0)].sum())
+        assert abs(g["stats"]["t_fallbacks"] - want) <= ties, (g["stats"]["t_fallbacks"], want)
 
 
 @pytest.mark.parametrize("method", [1, 2, 3])

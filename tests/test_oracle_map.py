@@ -87,6 +87,13 @@ def test_fov_wedge():
             assert oracle.in_fov(t, p, deg(a)), (fov, a)
         for a in outside:
             assert not oracle.in_fov(t, p, deg(a)), (fov, a)
+    # closed wedges: viewpoints exactly on the boundary are inside (45 and 135
+    # degrees from the normal for FOVs of 90 and 270 degrees), one lattice
+    # step further out they are not
+    for fov, on, off in ((90, (50.0, 50.0, 0.0), (50.00390625, 50.0, 0.0)),
+                         (270, (50.0, -50.0, 0.0), (49.99609375, -50.0, 0.0))):
+        assert oracle.in_fov(t, Params(fov_deg=fov), on), fov
+        assert not oracle.in_fov(t, Params(fov_deg=fov), off), fov
     # closed at 90 degrees for a 180-degree FOV: points on the target line are inside
     assert oracle.in_fov(t, Params(fov_deg=180), (50.0, 0.0, 0.0))
     assert not oracle.in_fov(t, Params(fov_deg=180), (50.0, -0.00390625, 0.0))

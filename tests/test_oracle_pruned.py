@@ -165,8 +165,202 @@ def test_pruned_gate_equals_brute_at_theta_one():
     scene, q = scenes.plain2d_50rects()
     for mode in (FULL, FRACTION):
         q.params.mode = mode
-        b = oracle.vcm_eval(scene, q)
+        b = oracle.vcm_eval(scene, q, nthreads=8)
         for m in (1, 2, 3):
-            p = oracle.vcm_eval_pruned(scene, q, m, 1)
+            p = oracle.vcm_eval_pruned(scene, q, m, 1, nthreads=8)
             assert np.array_equal(p["count"], b["count"])
             assert np.all((p["c"] > 0) == (b["c"] > 0))
+
+
+# ---------------------------------------------------------------------------
+# Selection rules of VCM_M and VCM_T and the cell colour, checked on tiny
+# partitions (large mu, so that rings are few and wide and the approximated
+# cells overlap a lot) against the geometry of the cells themselves.
+
+TINY = [(10.0, 5.0), (4.0, 3.0), (10.0, 12.0), (30.0, 2.0)]   # (S in m, mu in degrees)
+
+
+def _tiny(S, mu_deg):
+    return oracle.Cells(S, math.radians(mu_deg), 0.25)
+
+
+def _centre_colour(c, i, j):
+    """Visual angle (Eq. 1 with the oblique size of Eq. 2) at the centre of
+    cell (i, j) in parameter space -- the middle distance of the ring and the
+    middle angle of the band -- over V0."""
+    g = c.bands(i)
+    return V(c.S, 0.5 * (c.d[i] + c.d[i + 1]), 0.5 * (g[j] + g[j + 1])) / c.V0
+
+
+def _sector_mbr(r0, r1, g_lo, g_hi, n=257):
+    """Bounding box, in the (rho, h) quadrant, of the annular sector
+    {r in [r0, r1], angle in [g_lo, g_hi]}, from points of its boundary (the
+    arcs and the two radial edges, their end points included)."""
+    ang = np.linspace(g_lo, g_hi, n)
+    rr = np.linspace(r0, r1, n)
+    xs = np.concatenate([r0 * np.cos(ang), r1 * np.cos(ang), rr * math.cos(g_lo), rr * math.cos(g_hi)])
+    ys = np.concatenate([r0 * np.sin(ang), r1 * np.sin(ang), rr * math.sin(g_lo), rr * math.sin(g_hi)])
+    return xs.min(), xs.max(), ys.min(), ys.max()
+
+
+def _trapezoid(r0, r1, g_lo, g_hi):
+    """Corners, counter-clockwise, of the quadrilateral bounded by the band's
+    two radial edges and the tangents of the arcs r0 and r1 at the band's
+    middle angle."""
+    gm = 0.5 * (g_lo + g_hi)
+    out = []
+    for r, gs in ((r0, (g_hi, g_lo)), (r1, (g_lo, g_hi))):
+        for g in gs:
+            L = r / math.cos(g - gm)   # where the tangent line meets the edge ray
+            out.append((L * math.cos(g), L * math.sin(g)))
+    return out
+
+
+def _points(c, n, seed):
+    rng = np.random.default_rng(seed)
+    D = np.exp(rng.uniform(math.log(0.3), math.log(c.d[-1] * 0.999), n))
+    a = rng.uniform(0.0, math.pi / 2, n)
+    return D, a
+
+
+@pytest.mark.parametrize("S,mu_deg", TINY)
+def test_m_takes_the_lowest_cell_whose_mbr_holds_q(S, mu_deg):
+    """VCM_M (Sec. IV-A, MBR approximation): the colour of the first cell, in
+    (ring, band) order, whose bounding box holds q; the boxes here come from
+    points of the cells' boundaries, not from a closed form."""
+    c = _tiny(S, mu_deg)
+    cells = []
+    for i in range(c.nring):
+        g = c.bands(i)
+        for j in range(len(g) - 1):
+            cells.append((i, j, _sector_mbr(c.d[i], c.d[i + 1], g[j + 1], g[j])))
+    D, a = _points(c, 2500, int(S * 100 + mu_deg))
+    checked = other = 0
+    for Dk, ak in zip(D, a):
+        rho, h = Dk * math.cos(ak), Dk * math.sin(ak)
+        eps = 1e-9 * Dk
+        strict = [(i, j) for i, j, (x0, x1, y0, y1) in cells
+                  if x0 + eps <= rho <= x1 - eps and y0 + eps <= h <= y1 - eps]
+        loose = [(i, j) for i, j, (x0, x1, y0, y1) in cells
+                 if x0 - eps <= rho <= x1 + eps and y0 - eps <= h <= y1 + eps]
+        if not strict or strict[0] != loose[0]:
+            continue   # within rounding of some box's edge: either answer is right
+        i, j = strict[0]
+        r = c.colours(Dk, ak)
+        assert r["M"] == pytest.approx(_centre_colour(c, i, j), rel=1e-12, abs=1e-15), (Dk, ak)
+        checked += 1
+        other += (i, j) != (r["ring"], r["band"])
+    assert checked > 2000
+    assert other > 100, "too few viewpoints take another cell's colour to exercise the rule"
+
+
+@pytest.mark.parametrize("S,mu_deg", TINY)
+def test_t_takes_the_lowest_ring_whose_tangent_trapezoid_holds_q(S, mu_deg):
+    """VCM_T (Sec. IV-A, tangential approximation): the colour of the first
+    ring whose cell, cut by the tangents of its arcs at the middle of the
+    band, holds q; the quadrilaterals here are built from their corners and
+    tested with a generic point-in-convex-polygon rule.  No quadrilateral
+    holds q: q's own cell."""
+    c = _tiny(S, mu_deg)
+    order, polys = [], []
+    for i in range(c.nring):
+        g = c.bands(i)
+        for j in range(len(g) - 1):
+            order.append((i, j))
+            polys.append(_trapezoid(c.d[i], c.d[i + 1], g[j + 1], g[j]))
+    P = np.array(polys)                      # (cells, 4 corners, 2)
+    E0 = P                                   # edge starts
+    E1 = np.roll(P, -1, axis=1)              # edge ends
+    ex, ey = E1[..., 0] - E0[..., 0], E1[..., 1] - E0[..., 1]
+    el = np.hypot(ex, ey)
+    D, a = _points(c, 2500, int(S * 10 + mu_deg))
+    checked = other = 0
+    for Dk, ak in zip(D, a):
+        x, y = Dk * math.cos(ak), Dk * math.sin(ak)
+        side = (ex * (y - E0[..., 1]) - ey * (x - E0[..., 0])) / el   # left of every edge: inside
+        slack = 1e-9 * Dk
+        inside = np.all(side >= -slack, axis=1)
+        near = inside & np.any(np.abs(side) <= slack, axis=1)
+        hits = np.nonzero(inside)[0]
+        if len(hits) and near[hits[0]]:
+            continue   # within rounding of the first candidate's edge
+        r = c.colours(Dk, ak)
+        if len(hits) == 0:
+            assert r["t_fallback"] and r["T"] == r["E"]
+        else:
+            hit = order[hits[0]]
+            assert not r["t_fallback"]
+            assert r["T"] == pytest.approx(_centre_colour(c, *hit), rel=1e-12, abs=1e-15), (Dk, ak)
+            other += hit != (r["ring"], r["band"])
+        checked += 1
+    assert checked > 2000 and other > 20
+
+
+def test_t_single_band_rings_project_on_the_diagonal():
+    """A ring whose visual angle at its middle distance is below 2 mu has one
+    band, from 90 degrees down to 0; its tangents touch the arcs at 45
+    degrees, so the ring holds q under VCM_T exactly when the projection of q
+    on the diagonal, D cos(alpha - 45 deg), lies in the ring."""
+    c = _tiny(10.0, 12.0)
+    single = [i for i in range(c.nring) if len(c.bands(i)) == 2]
+    assert single
+    i = single[-1]
+    rng = np.random.default_rng(9)
+    n = 0
+    for _ in range(400):
+        a = rng.uniform(0.02, math.pi / 2 - 0.02)
+        p = rng.uniform(c.d[i] * 1.001, c.d[i + 1] * 0.999)
+        D = p / math.cos(a - math.pi / 4)
+        if D >= c.d[-1]:
+            continue
+        r = c.colours(D, a)
+        # lower rings cannot hold q: their trapezoids end below d_i in every direction
+        assert r["T"] == pytest.approx(_centre_colour(c, i, 0), rel=1e-12)
+        n += 1
+    assert n > 200
+
+
+@pytest.mark.parametrize("S,mu_deg", [(30.0, 4.0 / 60.0)] + TINY)
+def test_cell_colour_is_the_visual_angle_at_the_parameter_midpoint(S, mu_deg):
+    """A cell's colour is the visibility at its centre (Sec. III-A): here the
+    middle of the ring's distances and of the band's angles, through Eq. 1
+    and Eq. 2 (a colour taken at d_i, d_{i+1}, gamma_j or gamma_{j+1}
+    differs by at least one mu step)."""
+    c = _tiny(S, mu_deg)
+    rng = np.random.default_rng(int(S + 10 * mu_deg))
+    for _ in range(400):
+        i = int(rng.integers(0, c.nring))
+        g = c.bands(i)
+        j = int(rng.integers(0, len(g) - 1))
+        D = rng.uniform(c.d[i], c.d[i + 1]) if i > 0 else rng.uniform(0.01, c.d[1])
+        a = rng.uniform(g[j + 1], g[j])
+        r = c.colours(D, a)
+        if (r["ring"], r["band"]) != (i, j):
+            continue   # on a boundary after rounding
+        assert r["E"] == pytest.approx(_centre_colour(c, i, j), rel=1e-13)
+
+
+@pytest.mark.parametrize("dim,S,mu_deg", [(2, 10.0, 5.0), (2, 4.0, 3.0), (3, 10.0, 5.0), (3, 4.0, 3.0)])
+def test_measured_error_within_the_printed_bounds(dim, S, mu_deg):
+    """Sec. IV-A: the colouring error of the MBR and tangential
+    approximations, summed over the whole region of distinguishable
+    visibility as |V_approx - V_E| times the size each viewpoint stands for,
+    stays below E_MBR and E_Tangent.  The bounds are sums over the cells of
+    one meridian quadrant (2-D; the plane holds four) or of the half-space on
+    one side of the target plane (3-D; the space holds two).  Measured
+    ratios are small (about 0.02-0.3): the printed bounds are far from tight."""
+    c = _tiny(S, mu_deg)
+    m = 600 if dim == 2 else 90
+    step = c.d[-1] / m
+    xs = (np.arange(-m, m) + 0.5) * step
+    if dim == 2:
+        X, Y = np.meshgrid(xs, xs, indexing="ij")
+        rho, h, A, copies = np.abs(X).ravel(), np.abs(Y).ravel(), step ** 2, 4
+    else:
+        X, Y, Z = np.meshgrid(xs, xs, xs, indexing="ij")
+        rho, h, A, copies = np.hypot(X, Y).ravel(), np.abs(Z).ravel(), step ** 3, 2
+    got = c.bound_measured(np.hypot(rho, h), np.arctan2(h, rho), A)
+    bound = c.error_bounds(dim)
+    for k in ("mbr", "tangent"):
+        ratio = got[k] / (copies * bound[k])
+        assert 0.0 < ratio < 1.0, (k, ratio)
