@@ -152,7 +152,11 @@ typedef struct {
                               fraction of live samples                      */
     int32_t theta_blocks;  /* minimum block size, in viewpoints (1)          */
     double recheck_eps;    /* float32 slab-test margin in units of the ray
-                              parameter (2^-20); +inf rechecks every test   */
+                              parameter (2^-20); +inf rechecks every test.
+                              At least 2^-21: the float32 slab gap carries
+                              up to 3.5 * 2^-23 of rounding error, and a
+                              smaller margin would let float32 decide rays
+                              it cannot decide exactly (VCM_E_INVALID)     */
     int32_t precision;     /* VCM_FP32_RECHECK: float32 ray tests, exact
                               float64 recheck near the boundary, float32
                               measure; VCM_FP64: every ray test exact in
@@ -187,19 +191,40 @@ typedef struct {
                                 corridor over their own extent along the
                                 walk                                        */
     double kernel_ms;        /* device time of the call's kernels            */
+    /* Pruned methods only (0 otherwise): */
+    double err_signed;       /* Sec. V-A error, sum(c_ref - c) / sum(c_ref),
+                                c_ref the brute-force colour (VCM_PRUNED_E)
+                                or the VCM_PRUNED_E colour (_M, _T) under
+                                the same visibility gate                    */
+    double err_abs;          /* the same with |c_ref - c|                    */
+    double bound;            /* VCM_PRUNED_M / _T: E_MBR / E_Tangent of
+                                Sec. IV-A over the whole space (the printed
+                                sum over one meridian quadrant times 4 in
+                                2-D, over one half-space times 2 in 3-D)     */
+    double bound_measured;   /* the error that bound covers, over this grid:
+                                sum over viewpoints within d_max of
+                                |V_approx - V_E| (radians, no visibility
+                                gate) times the area (2-D) or volume (3-D)
+                                of one lattice cell                         */
 } vcm_stats;
 
-/* Results: caller-owned device buffers of grid.n[0]*n[1]*n[2] entries.
+/* Results: caller-owned buffers of grid.n[0]*n[1]*n[2] entries.
  *   bin   : colour bin, min(B-1, floor(c' B)) with c' the colour in the
  *           chosen scale (required);
  *   c     : colour in [0, 1] (optional, may be NULL);
  *   count : FRACTION mode: visible live samples; FULL mode: N(q) where
- *           every live sample is visible, else 0; 0 outside the FOV
- *           (optional, may be NULL). */
+ *           every live sample is visible, else 0 (the walk stops at the
+ *           first blocked ray, so a partial count is not known); 0 outside
+ *           the FOV (optional, may be NULL).
+ *   host  : 0: the buffers are device memory (every entry point);
+ *           1: host memory (vcm_compute only): the call computes into
+ *           device buffers of its own, copies the maps back and waits for
+ *           `stream` before returning. */
 typedef struct {
     uint8_t *bin;
     float *c;
     uint16_t *count;
+    int32_t host;
 } vcm_result;
 
 /* Compute one VCM.  Enqueues on `stream` and returns; the results are ready

@@ -449,6 +449,23 @@ static int check_query(int dim, const vo_target *t, const vo_grid *g, const vo_p
     return bad ? -1 : 0;
 }
 
+/* Closed bounding box of the target (its extent along each axis). */
+static void target_box(const vo_target *t, double *lo, double *hi)
+{
+    double half[3] = {0.0, 0.0, 0.0};
+    if (t->kind == VO_CUBE) {
+        half[0] = half[1] = half[2] = t->size[0] / 2.0;
+    } else {
+        half[1 - t->normal_axis] = t->size[0] / 2.0;
+        if (t->kind == VO_BILLBOARD)
+            half[2] = t->size[1] / 2.0;
+    }
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = t->center[k] - half[k];
+        hi[k] = t->center[k] + half[k];
+    }
+}
+
 /* Evaluate the VCM at the listed viewpoints (linear index, x fastest).
  * lo/hi: [3][nbox] SoA, multiples of 2^-8.  Any output pointer may be NULL.
  * count: FRACTION mode: visible live samples; FULL mode: N(q) when all are
@@ -474,6 +491,29 @@ int vo_eval(int dim, int64_t nbox, const double *lo, const double *hi,
                 return -1;
             }
         }
+    /* The target is not an obstacle (Def. 2.1 keeps them apart): a query
+     * whose target box meets a closed obstacle box is rejected. */
+    {
+        double tl[3], th[3];
+        int64_t TL[3] = {0, 0, 0}, TH[3] = {0, 0, 0};
+        target_box(t, tl, th);
+        for (int a = 0; a < dim; ++a)
+            if (to_quanta(tl[a], &TL[a]) || to_quanta(th[a], &TH[a])) {
+                free(blo);
+                free(bhi);
+                return -1;
+            }
+        for (int64_t b = 0; b < nbox; ++b) {
+            int meet = 1;
+            for (int a = 0; a < dim; ++a)
+                meet = meet && blo[3 * b + a] <= TH[a] && bhi[3 * b + a] >= TL[a];
+            if (meet) {
+                free(blo);
+                free(bhi);
+                return -1;
+            }
+        }
+    }
     if (nthreads < 1)
         nthreads = 1;
     if (nthreads > 256)

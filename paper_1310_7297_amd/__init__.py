@@ -27,7 +27,8 @@ VCM_FP32_RECHECK, VCM_FP64 = 0, 1
 
 # Every symbol include/vcm.h declares.
 EXPORTS = ("vcm_last_error", "vcm_version", "vcm_build_index", "vcm_free_index",
-           "vcm_index_get_info", "vcm_compute", "vcm_compute_batch", "vcm_batch_create",
+           "vcm_index_get_info", "vcm_compute", "vcm_compute_batch",
+           "vcm_batch_create",
            "vcm_batch_run", "vcm_batch_get_info", "vcm_batch_destroy", "vcm_server_create",
            "vcm_submit", "vcm_poll", "vcm_wait", "vcm_server_drain", "vcm_server_get_stats",
            "vcm_server_reset_stats", "vcm_server_destroy", "vcm_tune_cell_size", "vcm_map_error",
@@ -88,11 +89,14 @@ class vcm_stats(ctypes.Structure):
                 ("fp32_disagree", ctypes.c_uint64), ("columns", ctypes.c_uint64),
                 ("slot_tests", ctypes.c_uint64), ("inside_box", ctypes.c_uint64),
                 ("t_fallbacks", ctypes.c_uint64), ("records", ctypes.c_uint64),
-                ("narrow_tests", ctypes.c_uint64), ("kernel_ms", ctypes.c_double)]
+                ("narrow_tests", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
+                ("err_signed", ctypes.c_double), ("err_abs", ctypes.c_double),
+                ("bound", ctypes.c_double), ("bound_measured", ctypes.c_double)]
 
 
 class vcm_result(ctypes.Structure):
-    _fields_ = [("bin", ctypes.c_void_p), ("c", ctypes.c_void_p), ("count", ctypes.c_void_p)]
+    _fields_ = [("bin", ctypes.c_void_p), ("c", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("host", ctypes.c_int32)]
 
 
 class vcm_batch_opts(ctypes.Structure):
@@ -317,16 +321,20 @@ def vcm_compute(index: Index, query: scenes.Query, bin_out, c_out=None, count_ou
     """Enqueue one VCM on `stream` (default: torch's current stream).
 
     bin_out (uint8), c_out (float32), count_out (int16 storage of uint16) are
-    torch tensors on the device with one entry per viewpoint."""
+    torch tensors with one entry per viewpoint, all on the device, or all in
+    host memory (then the call returns once they are filled)."""
     L = load_library()
     Q = make_query(query, precision)
     n = query.grid.count
+    bufs = [t for t in (bin_out, c_out, count_out) if t is not None]
+    host = bool(bufs) and not bufs[0].is_cuda
     for t, name in ((bin_out, "bin"), (c_out, "c"), (count_out, "count")):
         if t is not None:
-            if not t.is_cuda or t.numel() < n or not t.is_contiguous():
-                raise ValueError(f"{name}: need a contiguous device tensor of >= {n} entries")
+            if t.is_cuda == host or t.numel() < n or not t.is_contiguous():
+                raise ValueError(f"{name}: need contiguous tensors of >= {n} entries, all on the device "
+                                 "or all in host memory")
     R = vcm_result(bin_out.data_ptr(), c_out.data_ptr() if c_out is not None else None,
-                   count_out.data_ptr() if count_out is not None else None)
+                   count_out.data_ptr() if count_out is not None else None, int(host))
     st = vcm_stats()
     _check(L.vcm_compute(index.handle, ctypes.byref(Q), ctypes.byref(R), _stream_ptr(stream),
                          ctypes.byref(st) if stats else None))

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <algorithm>
 
 #include "vcm_internal.h"
 
@@ -28,6 +29,38 @@ bool dyadic(double x) {
 }
 
 double deg2rad(double d) { return d * M_PI / 180.0; }
+
+// Does the closed box of the target (centre c, half extents half) meet a
+// closed obstacle box?  The target is not an obstacle, so an obstacle that
+// touches or enters it makes the query ill-posed (Def. 2.1 separates the
+// target from the obstacle set).  Scans the host copy of the columns the
+// target's footprint overlaps.
+bool target_meets_obstacle(const Index &ix, const double *c, const double *half) {
+    if (ix.h_col_start.empty()) return false;
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = c[k] - half[k] - ix.frame[k];
+        hi[k] = c[k] + half[k] - ix.frame[k];
+    }
+    const double cs = ix.dev.cs;
+    auto col = [&](double x, int n) {
+        return static_cast<int>(std::max(0.0, std::min(double(n - 1), std::floor(x / cs))));
+    };
+    const int x0 = col(lo[0], ix.dev.nx), x1 = col(hi[0], ix.dev.nx);
+    const int y0 = col(lo[1], ix.dev.ny), y1 = col(hi[1], ix.dev.ny);
+    for (int y = y0; y <= y1; ++y)
+        for (int x = x0; x <= x1; ++x) {
+            const int cidx = x + ix.dev.nx * y;
+            for (int32_t r = ix.h_col_start[cidx]; r < ix.h_col_start[cidx + 1]; ++r) {
+                const BoxRec &b = ix.h_recs[r];
+                if (b.id < 0) continue;  // the sentinel
+                bool meet = true;
+                for (int k = 0; k < ix.dim; ++k) meet = meet && b.lo[k] <= hi[k] && b.hi[k] >= lo[k];
+                if (meet) return true;
+            }
+        }
+    return false;
+}
 
 }  // namespace
 
@@ -84,6 +117,8 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
             !dyadic(T.center[1] + (2 * i + 1 - T.samples_v) * hv))
             return set_error(VCM_E_INVALID, "sample lattice off the 2^-8 lattice (size / samples_v)");
     const double S = T.kind == VCM_BILLBOARD ? std::max(T.size[0], T.size[1]) : T.size[0];
+    if (target_meets_obstacle(ix, T.center, half))
+        return set_error(VCM_E_INVALID, "the target's box meets an obstacle");
     // ---- grid
     int64_t count = 1;
     for (int k = 0; k < 3; ++k) {
@@ -115,7 +150,12 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
         return set_error(VCM_E_INVALID, "unknown method");
     if (P.theta_blocks < 1 || P.theta_blocks > 4096)
         return set_error(VCM_E_INVALID, "theta_blocks must be in [1, 4096]");
-    if (!(P.recheck_eps >= 0)) return set_error(VCM_E_INVALID, "recheck_eps must be >= 0");
+    // The float32 slab gap carries at most 3.5 * 2^-23 of rounding error (the
+    // reciprocal within 1 ulp, one rounding per product and one for the
+    // difference, on parameters in [0, 1]); a smaller margin would let
+    // float32 decide rays it cannot decide exactly.
+    if (!(P.recheck_eps >= kMinRecheckEps))
+        return set_error(VCM_E_INVALID, "recheck_eps must be at least 2^-21 (float32 error bound) or +inf");
     if (P.precision != VCM_FP32_RECHECK && P.precision != VCM_FP64)
         return set_error(VCM_E_INVALID, "unknown precision");
     const double mu = deg2rad(P.mu_arcmin / 60.0);
@@ -185,25 +225,57 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
     return VCM_OK;
 }
 
-vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
-                     int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats) {
-    const Tuning tune{};
-    if (method == VCM_BRUTE) return launch_brute(ix, t, g, p, r, s, stats, nullptr, 1, tune);
-    // pruned: gate at the block representatives, then the cell colours
-    int32_t gn[3];
+namespace {
+
+constexpr size_t kWsAlign = 256;
+size_t ws_align(size_t x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+int64_t block_count(const GridDesc &g, int theta, int32_t gn[3]) {
     int64_t nrep = 1;
     for (int k = 0; k < 3; ++k) {
         gn[k] = (g.n[k] + theta - 1) / theta;
         nrep *= gn[k];
     }
-    uint32_t *gate = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&gate), sizeof(uint32_t) * nrep, s);
-    if (e != hipSuccess) return set_error(VCM_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
-    vcm_status st = launch_brute(ix, t, g, p, r, s, stats, gate, theta, tune);
+    return nrep;
+}
+
+}  // namespace
+
+// Workspace layout: the work-item range counters, then (pruned methods) one
+// gate word per block and, with statistics, the colouring's partial sums.
+WsLayout query_workspace(const GridDesc &g, int method, int theta, bool stats) {
+    WsLayout w;
+    w.counter = 0;
+    size_t off = ws_align(kCounterBytes);
+    if (method != VCM_BRUTE && g.count > 0) {
+        int32_t gn[3];
+        w.gate = off;
+        off += ws_align(sizeof(uint32_t) * static_cast<size_t>(block_count(g, theta, gn)));
+        if (stats) {
+            w.sums = off;
+            w.n_sums = pruned_sum_blocks(g);
+            off += ws_align(sizeof(double) * kPrunedSums * static_cast<size_t>(w.n_sums));
+        }
+    }
+    w.bytes = off;
+    return w;
+}
+
+vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
+                     int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats,
+                     char *ws) {
+    const Tuning tune{};
+    const WsLayout w = query_workspace(g, method, theta, stats != nullptr);
+    unsigned *counter = reinterpret_cast<unsigned *>(ws + w.counter);
+    if (method == VCM_BRUTE) return launch_brute(ix, t, g, p, r, s, stats, nullptr, 1, tune, counter);
+    // pruned: gate at the block representatives, then the cell colours
+    int32_t gn[3];
+    block_count(g, theta, gn);
+    uint32_t *gate = reinterpret_cast<uint32_t *>(ws + w.gate);
+    vcm_status st = launch_brute(ix, t, g, p, r, s, stats, gate, theta, tune, counter);
     if (st == VCM_OK)
-        st = launch_pruned(ix, t, g, p, method, theta, gate, gn, r, s,
-                           stats ? &stats->t_fallbacks : nullptr);
-    hipFreeAsync(gate, s);
+        st = launch_pruned(ix, t, g, p, method, theta, gate, gn, r, s, stats ? &stats->t_fallbacks : nullptr,
+                           w.n_sums ? reinterpret_cast<double *>(ws + w.sums) : nullptr);
     return st;
 }
 
@@ -295,6 +367,7 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     clear_error();
     if (!index || !query || !result) return set_error(VCM_E_INVALID, "null argument");
     if (!result->bin) return set_error(VCM_E_INVALID, "result->bin is required");
+    if (result->host != 0 && result->host != 1) return set_error(VCM_E_INVALID, "result->host must be 0 or 1");
     const Index &ix = index->impl;
     TargetDesc t;
     GridDesc g;
@@ -303,7 +376,28 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     if (st != VCM_OK) return st;
     DeviceGuard guard(ix.device);
     hipStream_t s = (hipStream_t)stream;
+    const int method = query->params.method, theta = query->params.theta_blocks;
+    const WsLayout w = query_workspace(g, method, theta, stats != nullptr);
+    const size_t n = static_cast<size_t>(std::max<int64_t>(g.count, 0));
 
+    // Host result buffers: the maps are computed into device buffers of the
+    // call and copied back before it returns.
+    vcm_result dev = *result;
+    char *tmp = nullptr;
+    if (result->host) {
+        const size_t bytes = n * (1 + (result->c ? 4 : 0) + (result->count ? 2 : 0)) + 512;
+        TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&tmp), bytes, s));
+        size_t off = 0;
+        dev.c = result->c ? reinterpret_cast<float *>(tmp + off) : nullptr;
+        off += result->c ? (n * 4 + 255) / 256 * 256 : 0;
+        dev.count = result->count ? reinterpret_cast<uint16_t *>(tmp + off) : nullptr;
+        off += result->count ? (n * 2 + 255) / 256 * 256 : 0;
+        dev.bin = reinterpret_cast<uint8_t *>(tmp + off);
+        dev.host = 0;
+    }
+
+    char *ws = nullptr;
+    TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&ws), w.bytes, s));
     DevStats *d_stats = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (stats) {
@@ -313,19 +407,34 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
         TRY_HIP(hipMemsetAsync(d_stats, 0, sizeof(DevStats), s));
         TRY_HIP(hipEventRecord(e0, s));
     }
-    st = run_query(ix, t, g, p, query->params.method, query->params.theta_blocks, *result, s,
-                   d_stats);
-    if (!stats) return st;
-    TRY_HIP(hipEventRecord(e1, s));
+    st = run_query(ix, t, g, p, method, theta, dev, s, d_stats, ws);
+    if (stats && st == VCM_OK) TRY_HIP(hipEventRecord(e1, s));
+    std::vector<double> sums(static_cast<size_t>(w.n_sums) * kPrunedSums);
     DevStats h{};
-    TRY_HIP(hipMemcpyAsync(&h, d_stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
-    TRY_HIP(hipStreamSynchronize(s));
+    if (stats && st == VCM_OK) {
+        TRY_HIP(hipMemcpyAsync(&h, d_stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+        if (!sums.empty())
+            TRY_HIP(hipMemcpyAsync(sums.data(), ws + w.sums, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, s));
+    }
+    if (result->host && st == VCM_OK) {
+        TRY_HIP(hipMemcpyAsync(result->bin, dev.bin, n, hipMemcpyDeviceToHost, s));
+        if (result->c) TRY_HIP(hipMemcpyAsync(result->c, dev.c, n * 4, hipMemcpyDeviceToHost, s));
+        if (result->count) TRY_HIP(hipMemcpyAsync(result->count, dev.count, n * 2, hipMemcpyDeviceToHost, s));
+    }
+    hipFreeAsync(ws, s);
+    if (tmp) hipFreeAsync(tmp, s);
+    if (result->host || stats) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess && st == VCM_OK)
+            st = set_error(VCM_E_DEVICE, std::string("vcm_compute: ") + hipGetErrorString(e));
+    }
     float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(d_stats);
-    if (st != VCM_OK) return st;
+    if (e0 && e1 && st == VCM_OK) hipEventElapsedTime(&ms, e0, e1);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (d_stats) hipFree(d_stats);
+    if (st != VCM_OK || !stats) return st;
+    *stats = vcm_stats{};
     stats->viewpoints = (uint64_t)g.count;
     stats->rays = h.rays;
     stats->box_tests = h.box_tests;
@@ -338,6 +447,27 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     stats->records = h.records;
     stats->narrow_tests = h.narrow_tests;
     stats->kernel_ms = ms;
+    if (method != VCM_BRUTE) {
+        // Sec. V-A error against the reference map, and the Sec. IV-A
+        // comparison: the summed |V_approx - V_E| times the size each
+        // viewpoint stands for, against the bound over the whole space (the
+        // printed sums cover one meridian quadrant in 2-D, one half-space on
+        // a side of the target plane in 3-D)
+        double acc[kPrunedSums] = {0, 0, 0, 0};
+        for (int64_t b = 0; b < w.n_sums; ++b)
+            for (int k = 0; k < kPrunedSums; ++k) acc[k] += sums[static_cast<size_t>(b) * kPrunedSums + k];
+        stats->err_signed = acc[2] > 0 ? acc[0] / acc[2] : 0.0;
+        stats->err_abs = acc[2] > 0 ? acc[1] / acc[2] : 0.0;
+        if (method != VCM_PRUNED_E) {
+            double cell = 1.0;
+            for (int k = 0; k < ix.dim; ++k) cell *= query->grid.extent[k] / query->grid.n[k];
+            double bounds[2];
+            error_bounds(t.S, p.mu_d, p.d0_d, ix.dim, bounds);
+            const double copies = ix.dim == 2 ? 4.0 : 2.0;
+            stats->bound = copies * bounds[method == VCM_PRUNED_M ? 0 : 1];
+            stats->bound_measured = acc[3] * p.V0 * cell;
+        }
+    }
     return VCM_OK;
 }
 

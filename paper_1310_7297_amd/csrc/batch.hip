@@ -126,6 +126,8 @@ vcm_status BatchPlan::prepare(const Index &index, const vcm_query *qs, int nq, c
     for (int i = 0; i < nq; ++i) {
         PlanQuery pq{};
         if (!rs[i].bin) return set_error(VCM_E_INVALID, "result " + std::to_string(i) + ": bin is required");
+        if (rs[i].host)
+            return set_error(VCM_E_INVALID, "result " + std::to_string(i) + ": batches need device result buffers");
         vcm_status st = prepare_query(index, qs[i], &pq.t, &pq.g, &pq.p);
         if (st != VCM_OK) return set_error(st, "query " + std::to_string(i) + ": " + vcm_last_error());
         pq.method = qs[i].params.method;
@@ -224,7 +226,7 @@ vcm_status BatchPlan::enqueue(hipStream_t s, DevStats *stats) const {
         if (pq.method == VCM_BRUTE || pq.g.count <= 0) continue;
         vcm_status st = launch_pruned(*ix, pq.t, pq.g, pq.p, pq.method, pq.theta,
                                       reinterpret_cast<const uint32_t *>(d_base + pq.gate_off), pq.gn,
-                                      pq.r, s, stats ? &stats->t_fallbacks : nullptr);
+                                      pq.r, s, stats ? &stats->t_fallbacks : nullptr, nullptr);
         if (st != VCM_OK) return st;
     }
     return VCM_OK;

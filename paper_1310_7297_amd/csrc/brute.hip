@@ -1038,15 +1038,13 @@ vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, cons
 
 vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_in,
                         const ParamDesc &p, const vcm_result &r, hipStream_t stream,
-                        DevStats *stats, uint32_t *gate, int theta, const Tuning &tune) {
+                        DevStats *stats, uint32_t *gate, int theta, const Tuning &tune,
+                        unsigned *counter) {
     if (g_in.count <= 0) return VCM_OK;
     BruteArgs a = make_brute_args(ix, t, g_in, p, r, gate, theta, chunk_for(tune, p.mode));
     a.stats = stats;
     const int ns = slots_for(t);
     if (ns < 1 || ns > kMaxSlots) return set_error(VCM_E_INVALID, "too many target samples");
-    unsigned *counter = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&counter), kCounterBytes, stream);
-    if (e != hipSuccess) return set_error(VCM_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     a.counter = counter;
     const GridDesc &g = a.grid;
     const int64_t cpr = (g.n[0] + a.chunk - 1) / a.chunk;
@@ -1066,13 +1064,9 @@ vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_
             hipLaunchKernelGGL((k_brute<V::DIM, V::NS, V::E, V::MODE, V::ST>), grid, dim3(256), 0, stream, a,
                                a.idx.col_start, a.idx.recs);
         });
-        e = hipGetLastError();
-        if (e != hipSuccess) {
-            hipFreeAsync(counter, stream);
-            return set_error(VCM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
-        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return set_error(VCM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     }
-    hipFreeAsync(counter, stream);
     return VCM_OK;
 }
 

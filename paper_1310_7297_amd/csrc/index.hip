@@ -213,6 +213,12 @@ vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, i
                        ix->d_col_start, ncols, d_recs);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(stream));
+    // host copy of the lists, for argument checks that need the obstacles
+    ix->h_col_start.resize(static_cast<size_t>(ncols) + 1);
+    ix->h_recs.resize(static_cast<size_t>(std::max(total, 1)));
+    HIP_TRY(hipMemcpy(ix->h_col_start.data(), ix->d_col_start, sizeof(int32_t) * (ncols + 1),
+                      hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ix->h_recs.data(), d_recs, sizeof(BoxRec) * std::max(total, 1), hipMemcpyDeviceToHost));
     hipFree(d_lo);
     hipFree(d_hi);
     hipFree(d_counts);

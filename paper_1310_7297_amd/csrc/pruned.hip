@@ -128,6 +128,19 @@ __device__ inline int first_gamma_below(const CellFrame &F, const Ring &r, doubl
     return k;
 }
 
+// Sums of one pruned map, when statistics are requested (float64, one set per
+// workgroup, added on the host in workgroup order):
+//   [0] sum of (c_ref - c), [1] sum of |c_ref - c|, [2] sum of c_ref, where c
+//       is the map's colour and c_ref, under the same visibility gate, the
+//       brute-force colour (VCM_E) or the VCM_E colour (VCM_M, VCM_T): the
+//       error measure of Sec. V-A;
+//   [3] VCM_M / VCM_T: sum of |c_approx - c_E| over the viewpoints within
+//       d_max, without the visibility gate: the error the bounds of Sec. IV-A
+//       bound (they ignore obstacles), in colour units.
+struct PrunedSums {
+    double d[kPrunedSums];
+};
+
 struct PrunedArgs {
     CellFrame F;
     TargetDesc tgt;
@@ -142,11 +155,87 @@ struct PrunedArgs {
     float *c;
     uint16_t *count;
     unsigned long long *fallback;  // tangent lookups that fell back (optional)
+    double *sums;                  // per-workgroup PrunedSums (optional)
 };
 
-__global__ __launch_bounds__(256) void k_pruned(PrunedArgs A) {
-    const int64_t vp = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (vp >= A.grid.count) return;
+// Workgroup sum of the PrunedSums of its threads, written by thread 0.
+__device__ void write_sums(double *out, const PrunedSums &v) {
+    __shared__ double s[kPrunedSums][256];
+    for (int k = 0; k < kPrunedSums; ++k) s[k][threadIdx.x] = v.d[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w)
+            for (int k = 0; k < kPrunedSums; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kPrunedSums; ++k) out[kPrunedSums * blockIdx.x + k] = s[k][0];
+}
+
+// VCM_M: the colour of the lowest ring, then lowest band, whose closed MBR
+// in the (rho, h) quadrant contains q; q's own cell (ring iq, colour ce)
+// holds it, so the search ends there.
+__device__ double m_colour(const CellFrame &F, double D, double rho, double hh, int iq, double ce) {
+    // a ring's MBRs lie within sqrt(2) d_{i+1} of the centre
+    int i0 = ring_of(F, D / sqrt(2.0));
+    i0 = i0 < 0 ? 0 : i0;
+    while (i0 > 0 && sqrt(2.0) * ring_d(F, i0) >= D) --i0;
+    // tighter: with u = sin g_j, v = cos g_{j+1} of a band of width w,
+    // u^2 + v^2 <= 1 + 2w, so a ring whose MBR holds q has
+    // D^2 <= d_{i+1}^2 (1 + 2w)
+    {
+        const double w = widest_band(F, ring_d(F, i0), ring_d(F, iq + 1));
+        const int i1 = ring_of(F, D / sqrt(1.0 + 2.0 * w)) - 1;
+        if (i1 > i0) i0 = i1;
+    }
+    for (int i = i0; i <= iq; ++i) {
+        if (sqrt(2.0) * ring_d(F, i + 1) < D) continue;
+        const Ring r = make_ring(F, i);
+        // rho <= d_{i+1} cos(gamma_{j+1})  <=>  gamma_{j+1} <= acos(rho / d_{i+1})
+        int jB = rho <= r.dh ? first_gamma_below(F, r, acos(rho / r.dh)) - 1 : r.L + 1;
+        // d_i sin(gamma_{j+1}) <= h  <=>  gamma_{j+1} <= asin(h / d_i)
+        int jC = hh >= r.dl ? 0 : first_gamma_below(F, r, asin(hh / r.dl)) - 1;
+        jB = max(jB, 0);
+        jC = max(jC, 0);
+        const int j = max(jB, jC);
+        if (j > r.L) continue;
+        const double g0 = gamma_of(F, r, j), g1 = gamma_of(F, r, j + 1);
+        if (rho >= r.dl * cos(g0) && rho <= r.dh * cos(g1) && hh >= r.dl * sin(g1) && hh <= r.dh * sin(g0))
+            return cell_colour(F, r, j);
+    }
+    return ce;
+}
+
+// VCM_T: the colour of the lowest ring whose tangent trapezoid (band of
+// alpha, projection on the band's middle direction in [d_i, d_{i+1}))
+// contains q; q's own cell if none does (*fell_back set).
+__device__ double t_colour(const CellFrame &F, double D, double alpha, int iq, double ce, bool *fell_back) {
+    // the projection is at least D cos(45 deg)
+    int i0 = ring_of(F, D * sqrt(0.5));
+    i0 = i0 < 0 ? 0 : i0;
+    while (i0 > 0 && ring_d(F, i0) > D * sqrt(0.5)) --i0;
+    // tighter: alpha lies in the band, within half a band width of its
+    // middle, so the projection is at least D cos(w / 2)
+    {
+        const double w = widest_band(F, ring_d(F, i0), ring_d(F, iq + 1));
+        const int i1 = ring_of(F, D * cos(0.5 * w)) - 1;
+        if (i1 > i0) i0 = i1;
+    }
+    for (int i = i0; i <= iq; ++i) {
+        const Ring r = make_ring(F, i);
+        const int j = band_of(F, r, alpha);
+        const double gm = 0.5 * (gamma_of(F, r, j) + gamma_of(F, r, j + 1));
+        const double p = D * cos(alpha - gm);
+        if (p >= r.dl && p < r.dh) {
+            *fell_back = false;
+            return cell_colour(F, r, j);
+        }
+    }
+    *fell_back = true;
+    return ce;
+}
+
+__device__ void colour_viewpoint(const PrunedArgs &A, int64_t vp, PrunedSums &sum) {
     const int n0 = A.grid.n[0], n1 = A.grid.n[1];
     const int ii[3] = {static_cast<int>(vp % n0), static_cast<int>((vp / n0) % n1),
                        static_cast<int>(vp / (static_cast<int64_t>(n0) * n1))};
@@ -179,85 +268,31 @@ __global__ __launch_bounds__(256) void k_pruned(PrunedArgs A) {
     const uint32_t gw = A.gate[rep];
     const int vis = static_cast<int>(gw & 1023u), N = static_cast<int>((gw >> 10) & 1023u);
     const bool fov = (gw >> 20) & 1u;
+    const bool shown = fov && N > 0 && vis > 0;   // some colour survives the gate
 
     const CellFrame &F = A.F;
-    double craw = 0.0;
+    double craw = 0.0, ce = 0.0;
     bool fell_back = false;
     const int iq = ring_of(F, D);
-    if (iq >= 0 && fov && N > 0 && vis > 0) {
+    if (iq >= 0 && (shown || A.sums)) {
         const Ring rq = make_ring(F, iq);
-        const int jq = band_of(F, rq, alpha);
-        const double ce = cell_colour(F, rq, jq);
+        ce = cell_colour(F, rq, band_of(F, rq, alpha));
         craw = ce;
-        if (A.method == VCM_PRUNED_M) {
-            // lowest ring, then lowest band, whose closed MBR contains (rho, h);
-            // a ring's MBRs lie within sqrt(2) d_{i+1} of the centre
-            int i0 = ring_of(F, D / sqrt(2.0));
-            i0 = i0 < 0 ? 0 : i0;
-            while (i0 > 0 && sqrt(2.0) * ring_d(F, i0) >= D) --i0;
-            // tighter: with u = sin g_j, v = cos g_{j+1} of a band of width w,
-            // u^2 + v^2 <= 1 + 2w, so a ring whose MBR holds q has
-            // D^2 <= d_{i+1}^2 (1 + 2w)
-            {
-                const double w = widest_band(F, ring_d(F, i0), ring_d(F, iq + 1));
-                const int i1 = ring_of(F, D / sqrt(1.0 + 2.0 * w)) - 1;
-                if (i1 > i0) i0 = i1;
-            }
-            bool found = false;
-            for (int i = i0; i <= iq && !found; ++i) {
-                if (sqrt(2.0) * ring_d(F, i + 1) < D) continue;
-                const Ring r = make_ring(F, i);
-                // rho <= d_{i+1} cos(gamma_{j+1})  <=>  gamma_{j+1} <= acos(rho / d_{i+1})
-                int jB = rho <= r.dh ? first_gamma_below(F, r, acos(rho / r.dh)) - 1 : r.L + 1;
-                // d_i sin(gamma_{j+1}) <= h  <=>  gamma_{j+1} <= asin(h / d_i)
-                int jC = hh >= r.dl ? 0 : first_gamma_below(F, r, asin(hh / r.dl)) - 1;
-                jB = max(jB, 0);
-                jC = max(jC, 0);
-                const int j = max(jB, jC);
-                if (j > r.L) continue;
-                const double g0 = gamma_of(F, r, j), g1 = gamma_of(F, r, j + 1);
-                const bool in = rho >= r.dl * cos(g0) && rho <= r.dh * cos(g1) &&
-                                hh >= r.dl * sin(g1) && hh <= r.dh * sin(g0);
-                if (in) {
-                    craw = cell_colour(F, r, j);
-                    found = true;
-                }
-            }
-        } else if (A.method == VCM_PRUNED_T) {
-            // lowest ring whose tangent trapezoid (band of alpha, projection on
-            // the band's middle direction in [d_i, d_{i+1})) contains q; the
-            // projection is at least D cos(45 deg)
-            int i0 = ring_of(F, D * sqrt(0.5));
-            i0 = i0 < 0 ? 0 : i0;
-            while (i0 > 0 && ring_d(F, i0) > D * sqrt(0.5)) --i0;
-            // tighter: alpha lies in the band, within half a band width of its
-            // middle, so the projection is at least D cos(w / 2)
-            {
-                const double w = widest_band(F, ring_d(F, i0), ring_d(F, iq + 1));
-                const int i1 = ring_of(F, D * cos(0.5 * w)) - 1;
-                if (i1 > i0) i0 = i1;
-            }
-            bool found = false;
-            for (int i = i0; i <= iq && !found; ++i) {
-                const Ring r = make_ring(F, i);
-                const int j = band_of(F, r, alpha);
-                const double gm = 0.5 * (gamma_of(F, r, j) + gamma_of(F, r, j + 1));
-                const double p = D * cos(alpha - gm);
-                if (p >= r.dl && p < r.dh) {
-                    craw = cell_colour(F, r, j);
-                    found = true;
-                }
-            }
-            fell_back = !found;
-        }
+        if (A.method == VCM_PRUNED_M) craw = m_colour(F, D, rho, hh, iq, ce);
+        else if (A.method == VCM_PRUNED_T) craw = t_colour(F, D, alpha, iq, ce, &fell_back);
     }
-    double col = 0.0;
-    int cnt = vis;
-    if (fov && N > 0) {
-        if (A.prm.mode == VCM_FRACTION)
-            col = (double(vis) / double(N)) * craw;
-        else
-            col = vis == N ? craw : 0.0;
+    double gatef = 0.0;
+    if (fov && N > 0) gatef = A.prm.mode == VCM_FRACTION ? double(vis) / double(N) : (vis == N ? 1.0 : 0.0);
+    const double col = gatef * craw;
+    if (A.sums) {
+        // reference colour under the same gate: the brute-force measure for
+        // VCM_E, q's own cell for VCM_M and VCM_T
+        const double ref_raw = A.method == VCM_PRUNED_E ? vis_angle(F.S, D > F.d0 ? D : F.d0, alpha) / F.V0 : ce;
+        const double ref = gatef * ref_raw;
+        sum.d[0] += ref - col;
+        sum.d[1] += fabs(ref - col);
+        sum.d[2] += ref;
+        if (A.method != VCM_PRUNED_E) sum.d[3] += fabs(craw - ce);
     }
     double cb = col;
     if (A.prm.bin_scale == VCM_BIN_LOG) {
@@ -268,11 +303,20 @@ __global__ __launch_bounds__(256) void k_pruned(PrunedArgs A) {
     const int bn = min(A.prm.n_bins - 1, static_cast<int>(floor(cb * A.prm.n_bins)));
     A.bin[vp] = static_cast<uint8_t>(bn);
     if (A.c) A.c[vp] = static_cast<float>(col);
-    if (A.count) A.count[vp] = static_cast<uint16_t>(cnt);
-    if (A.fallback && fell_back) atomicAdd(A.fallback, 1ull);
+    if (A.count) A.count[vp] = static_cast<uint16_t>(vis);
+    if (A.fallback && fell_back && shown) atomicAdd(A.fallback, 1ull);
+}
+
+__global__ __launch_bounds__(256) void k_pruned(PrunedArgs A) {
+    const int64_t vp = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    PrunedSums sum{};
+    if (vp < A.grid.count) colour_viewpoint(A, vp, sum);
+    if (A.sums) write_sums(A.sums, sum);
 }
 
 }  // namespace
+
+int64_t pruned_sum_blocks(const GridDesc &g) { return (g.count + 255) / 256; }
 
 int count_rings(double S, double mu, double d0, double *V0) {
     *V0 = 2.0 * std::atan(S / (2.0 * d0));
@@ -287,7 +331,7 @@ int count_rings(double S, double mu, double d0, double *V0) {
 vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g,
                          const ParamDesc &p, int method, int theta, const uint32_t *gate,
                          const int32_t gn[3], const vcm_result &r, hipStream_t stream,
-                         unsigned long long *fallback) {
+                         unsigned long long *fallback, double *sums) {
     PrunedArgs a{};
     double V0;
     const double mu = p.mu_d;
@@ -309,7 +353,9 @@ vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g
     a.c = r.c;
     a.count = r.count;
     a.fallback = fallback;
-    const int64_t nblk = (g.count + 255) / 256;
+    a.sums = sums;
+    const int64_t nblk = pruned_sum_blocks(g);
+    if (nblk <= 0) return VCM_OK;
     hipLaunchKernelGGL(k_pruned, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)

@@ -267,6 +267,7 @@ vcm_status vcm_submit(vcm_server *server, const vcm_query *query, const vcm_resu
     clear_error();
     if (!server || !query || !result || !ticket) return set_error(VCM_E_INVALID, "null argument");
     if (!result->bin) return set_error(VCM_E_INVALID, "result->bin is required");
+    if (result->host) return set_error(VCM_E_INVALID, "served requests need device result buffers");
     // validate now, so that a bad request fails at submit, not in the engine
     TargetDesc t;
     GridDesc g;

@@ -17,6 +17,9 @@ namespace vcm {
 // position error is below 2^-9 m for scenes within 2^14 m.
 constexpr float kFatMargin = 1.0f / 64.0f;
 
+// Smallest float32 slab-test margin accepted (see prepare_query).
+constexpr double kMinRecheckEps = 0x1p-21;
+
 // Largest number of live samples per viewpoint (64-lane slots x 6).
 constexpr int kMaxSamples = 384;
 constexpr int kMaxSlots = 6;
@@ -97,6 +100,10 @@ struct ParamDesc {
     int32_t fp64;       // every ray test exact in float64, measure in float64
 };
 
+// Per-workgroup float64 partial sums of the pruned colouring, summed on the
+// host in a fixed order (see PrunedSums in pruned.hip).
+constexpr int kPrunedSums = 4;
+
 // Counters gathered when statistics are requested (atomically accumulated).
 struct DevStats {
     unsigned long long rays;
@@ -165,8 +172,10 @@ struct Index {
     double frame[3] = {0, 0, 0};  // world coordinates of the frame origin
     size_t bytes = 0;
     double build_ms = 0.0;
-    // Host copy of the boxes (float32, exact), used for validation.
-    std::string scene_key;
+    // Host copy of the column lists (same layout as on the device), used to
+    // reject targets that meet an obstacle.
+    std::vector<int32_t> h_col_start;
+    std::vector<BoxRec> h_recs;
 };
 
 // Makes `dev` current for the lifetime of the guard.
@@ -191,10 +200,13 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
                          ParamDesc *p);
 
 // Launch the brute-force kernel over the whole grid of one query on `stream`
-// (gate mode: over the representatives of the theta-blocks).
+// (gate mode: over the representatives of the theta-blocks).  `counter`
+// holds kCounterBytes of device memory (the work-item range counters; the
+// launch clears them with a kernel first).
 vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g,
                         const ParamDesc &p, const vcm_result &r, hipStream_t stream,
-                        DevStats *stats, uint32_t *gate, int theta, const Tuning &tune);
+                        DevStats *stats, uint32_t *gate, int theta, const Tuning &tune,
+                        unsigned *counter);
 
 // Pieces of a batched launch.
 int device_cus(int device);
@@ -210,18 +222,35 @@ vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, cons
                               hipStream_t s);
 
 // Pruned colouring (E / M / T) of every viewpoint from the block gates.
+// With `sums` non-null (pruned_sum_blocks(g) x kPrunedSums doubles), each
+// workgroup also writes its partial sums of the Sec. V-A error and of the
+// Sec. IV-A measured error (see pruned.hip).
 vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g,
                          const ParamDesc &p, int method, int theta, const uint32_t *gate,
                          const int32_t gn[3], const vcm_result &r, hipStream_t stream,
-                         unsigned long long *fallback);
+                         unsigned long long *fallback, double *sums);
+int64_t pruned_sum_blocks(const GridDesc &g);
 int count_rings(double S, double mu, double d0, double *V0);
 
 vcm_status map_error(const float *ce, const float *ca, int64_t n, hipStream_t s, double *out);
 void error_bounds(double S, double mu, double d0, int dim, double *out);
 
+// Device scratch memory one query needs beside its inputs and outputs, as
+// byte offsets into one buffer: the work-item counters, the pruned methods'
+// block gates, and (pruned methods with statistics) the colouring's partial
+// sums.
+struct WsLayout {
+    size_t counter = 0, gate = 0, sums = 0, bytes = 0;
+    int64_t n_sums = 0;  // workgroups writing PrunedSums (0: none)
+};
+WsLayout query_workspace(const GridDesc &g, int method, int theta, bool stats);
+
 // One query on one stream: brute force, or gates plus pruned colouring.
+// `ws` is device memory laid out as query_workspace(g, method, theta,
+// stats != nullptr), 256-byte aligned; its contents on entry do not matter.
 vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
-                     int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats);
+                     int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats,
+                     char *ws);
 
 // Pinned host buffers for host-to-device uploads, reused once the copies
 // that read them have completed (tracked by an event per buffer).

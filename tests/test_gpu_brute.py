@@ -212,10 +212,42 @@ def test_invalid_queries_rejected():
         Query(q.target, Grid((0.0, 0.0, 0.0), (1000.0, 1000.0, 0.0), (3, 64, 1)), q.params),
         Query(Target(CUBE, (500.0, 500.0, 0.0), (4.0, 0.0)), q.grid, q.params),
     ]
+    bad += [_with(q, recheck_eps=0.0), _with(q, recheck_eps=2.0 ** -22)]
     import torch
     b, c, cnt = vcm.alloc_result(q.grid.count)
     for bq in bad:
         with pytest.raises(vcm.VcmError) as e:
             vcm.vcm_compute(idx, bq, b, c, cnt)
         assert e.value.status == vcm.VCM_E_INVALID
+    vcm.vcm_compute(idx, _with(q, recheck_eps=2.0 ** -21), b, c, cnt)   # the smallest margin accepted
+    # a target whose box meets an obstacle (here one of the scene's own boxes)
+    k = 7
+    lo, hi = scene.lo[:, k], scene.hi[:, k]
+    t = Target(SEGMENT, (float(hi[0]) + 2.0, float(lo[1]), 0.0), (4.0, 0.0), normal_axis=1, samples_u=8,
+               samples_v=1)
+    with pytest.raises(vcm.VcmError) as e:
+        vcm.vcm_compute(idx, Query(t, q.grid, q.params), b, c, cnt)
+    assert e.value.status == vcm.VCM_E_INVALID and "obstacle" in str(e.value)
+    idx.free()
+
+
+def test_host_result_buffers():
+    """Result buffers in host memory: the call computes into device buffers of
+    its own and copies the maps back; the same maps as device buffers."""
+    import torch
+    scene, q = scenes.plain2d_50rects()
+    idx = vcm.vcm_build_index(scene)
+    dev = vcm.compute_map(idx, q)
+    n = q.grid.count
+    hb = torch.full((n,), 0xAB, dtype=torch.uint8)
+    hc = torch.full((n,), -1.0, dtype=torch.float32)
+    hn = torch.full((n,), -1, dtype=torch.int16)
+    vcm.vcm_compute(idx, q, hb, hc, hn)
+    assert np.array_equal(hb.numpy(), dev["bin"]) and np.array_equal(hc.numpy(), dev["c"])
+    assert np.array_equal(hn.numpy().view(np.uint16), dev["count"])
+    hb2 = torch.zeros(n, dtype=torch.uint8)
+    vcm.vcm_compute(idx, q, hb2)                     # bins only
+    assert np.array_equal(hb2.numpy(), dev["bin"])
+    with pytest.raises(ValueError):                  # mixed host and device buffers
+        vcm.vcm_compute(idx, q, hb, torch.empty(n, dtype=torch.float32, device="cuda"))
     idx.free()

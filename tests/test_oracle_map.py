@@ -215,3 +215,23 @@ def test_rejects_invalid():
     q.params.n_bins = 1
     with pytest.raises(ValueError):
         oracle.vcm_eval(s, q)
+
+
+def test_rejects_target_meeting_an_obstacle():
+    """The target is not an obstacle (Def. 2.1): a box that touches or enters
+    the target's box makes the query invalid; one lattice step away is fine."""
+    t = Target(BILLBOARD, (0.0, 0.0, 5.0), (8.0, 4.0), normal_axis=1, samples_u=8, samples_v=4)
+    g = Grid((-8.0, -40.0, 0.0), (16.0, 16.0, 16.0), (2, 2, 2))
+    q = Query(t, g, Params())
+    # the billboard spans x in [-4, 4], y = 0, z in [3, 7]
+    for lo, hi, bad in (((4.0, -1.0, 0.0), (6.0, 1.0, 9.0), True),          # touches the edge x = 4
+                        ((-1.0, 0.0, 0.0), (1.0, 2.0, 3.0), True),          # touches the bottom corner line
+                        ((-1.0, -1.0, 4.0), (1.0, 1.0, 5.0), True),         # goes through it
+                        ((4.00390625, -1.0, 0.0), (6.0, 1.0, 9.0), False),  # one step beside it
+                        ((-1.0, 0.0, 0.0), (1.0, 2.0, 2.99609375), False)):  # one step below
+        sc = Scene(3, np.array(lo, dtype=float).reshape(3, 1), np.array(hi, dtype=float).reshape(3, 1))
+        if bad:
+            with pytest.raises(ValueError):
+                oracle.vcm_eval(sc, q)
+        else:
+            oracle.vcm_eval(sc, q)
