@@ -233,6 +233,20 @@ typedef struct {
 vcm_status vcm_compute(const vcm_index *index, const vcm_query *query,
                        const vcm_result *result, void *stream, vcm_stats *stats);
 
+/* vcm_compute without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same results as vcm_compute; no statistics.  Its scratch
+ * memory (the work-item counters and the pruned methods' block gates) is a
+ * static device array of 64 MiB, one per device, held from the first call
+ * on that device until the process ends.  A query that needs more scratch
+ * than that fails with VCM_E_INVALID before any device work: a brute-force
+ * map needs 2 KiB, a pruned map 4 bytes per theta-block more.  Every call on
+ * one device shares the array, so calls that overlap on a device (other
+ * streams, other threads) race; the caller must order them.  Enqueues on
+ * `stream` and returns; results as for vcm_compute. */
+vcm_status vcm_compute_noalloc(const vcm_index *index, const vcm_query *query,
+                               const vcm_result *result, void *stream);
+
 /* ---------------------------------------------------------------- batches --- */
 
 /* Many queries on one index (each query is a Def. 2.1 problem of its own;

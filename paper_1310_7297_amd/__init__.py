@@ -27,7 +27,7 @@ VCM_FP32_RECHECK, VCM_FP64 = 0, 1
 
 # Every symbol include/vcm.h declares.
 EXPORTS = ("vcm_last_error", "vcm_version", "vcm_build_index", "vcm_free_index",
-           "vcm_index_get_info", "vcm_compute", "vcm_compute_batch",
+           "vcm_index_get_info", "vcm_compute", "vcm_compute_noalloc", "vcm_compute_batch",
            "vcm_batch_create",
            "vcm_batch_run", "vcm_batch_get_info", "vcm_batch_destroy", "vcm_server_create",
            "vcm_submit", "vcm_poll", "vcm_wait", "vcm_server_drain", "vcm_server_get_stats",
@@ -169,6 +169,8 @@ def load_library(path: Optional[str] = None):
     L.vcm_compute.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_query),
                               ctypes.POINTER(vcm_result), ctypes.c_void_p,
                               ctypes.POINTER(vcm_stats)]
+    L.vcm_compute_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_query),
+                                      ctypes.POINTER(vcm_result), ctypes.c_void_p]
     L.vcm_map_error.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_double * 2)]
     L.vcm_error_bounds.argtypes = [ctypes.POINTER(vcm_query), ctypes.c_int32,
@@ -197,6 +199,7 @@ def load_library(path: Optional[str] = None):
                                      ctypes.c_int32, ctypes.POINTER(vcm_tune_opts),
                                      ctypes.POINTER(vcm_tune_result)]
     for name in ("vcm_build_index", "vcm_free_index", "vcm_index_get_info", "vcm_compute",
+                 "vcm_compute_noalloc",
                  "vcm_compute_batch", "vcm_batch_create", "vcm_batch_run", "vcm_batch_get_info",
                  "vcm_batch_destroy", "vcm_server_create", "vcm_submit", "vcm_poll", "vcm_wait",
                  "vcm_server_drain", "vcm_server_get_stats", "vcm_server_reset_stats",
@@ -341,6 +344,16 @@ def vcm_compute(index: Index, query: scenes.Query, bin_out, c_out=None, count_ou
     if stats:
         return {f: getattr(st, f) for f, _ in vcm_stats._fields_}
     return None
+
+
+def vcm_compute_noalloc(index: Index, query: scenes.Query, bin_out, c_out=None, count_out=None,
+                        stream=None, precision: int = VCM_FP32_RECHECK):
+    """vcm_compute_noalloc: as vcm_compute, with the library's static scratch
+    memory instead of allocations (no statistics)."""
+    Q = make_query(query, precision)
+    R = _make_result(query.grid.count, bin_out, c_out, count_out)
+    _check(load_library().vcm_compute_noalloc(index.handle, ctypes.byref(Q), ctypes.byref(R),
+                                              _stream_ptr(stream)))
 
 
 def _make_result(n, bin_out, c_out=None, count_out=None) -> vcm_result:

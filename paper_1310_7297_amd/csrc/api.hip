@@ -1,6 +1,7 @@
 // C-ABI entry points: argument validation, ownership, launches.
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -279,6 +280,38 @@ vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, co
     return st;
 }
 
+// ------------------------------------------------ allocation-free scratch ---
+
+// Scratch memory of vcm_compute_noalloc: one copy per device, held until the
+// process ends.  Host code must not use this name as a device address (it is
+// a host-side stand-in there); scratch_address() gives the device's own
+// address, taken once per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+// Device address of `scratch` on `device`, which must be current.
+vcm_status scratch_address(int device, char **out) {
+    if (device < 0 || device >= kMaxDevices) return set_error(VCM_E_INVALID, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return set_error(VCM_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return VCM_OK;
+}
+
 }  // namespace vcm
 
 using namespace vcm;
@@ -469,6 +502,31 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
         }
     }
     return VCM_OK;
+}
+
+vcm_status vcm_compute_noalloc(const vcm_index *index, const vcm_query *query,
+                               const vcm_result *result, void *stream) {
+    clear_error();
+    if (!index || !query || !result) return set_error(VCM_E_INVALID, "null argument");
+    if (!result->bin) return set_error(VCM_E_INVALID, "result->bin is required");
+    if (result->host) return set_error(VCM_E_INVALID, "vcm_compute_noalloc needs device result buffers");
+    const Index &ix = index->impl;
+    TargetDesc t;
+    GridDesc g;
+    ParamDesc p;
+    vcm_status st = prepare_query(ix, *query, &t, &g, &p);
+    if (st != VCM_OK) return st;
+    const int method = query->params.method, theta = query->params.theta_blocks;
+    const size_t need = query_workspace(g, method, theta, false).bytes;
+    if (need > kScratchBytes)
+        return set_error(VCM_E_INVALID, "vcm_compute_noalloc: the query needs " + std::to_string(need) +
+                                            " bytes of scratch memory, more than the " +
+                                            std::to_string(kScratchBytes) + " bytes it has");
+    DeviceGuard guard(ix.device);
+    char *ws = nullptr;
+    st = scratch_address(ix.device, &ws);
+    if (st != VCM_OK) return st;
+    return run_query(ix, t, g, p, method, theta, *result, (hipStream_t)stream, nullptr, ws);
 }
 
 vcm_status vcm_map_error(const float *c_exact, const float *c_approx, int64_t n, int device,
