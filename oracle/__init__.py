@@ -212,7 +212,15 @@ def _plib():
                                      ctypes.POINTER(VoParams), ctypes.c_int, ctypes.c_int,
                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+        L.vo_hull_meets_box.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 5
+        L.vo_hull_meets_box.restype = ctypes.c_int
+        L.vo_classify_block.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(VoTarget), ctypes.POINTER(VoGrid),
+                                        ctypes.POINTER(VoParams), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
+        L.vo_classify_block.restype = ctypes.c_int
         L.vo_eval_pruned.restype = ctypes.c_int
         L.vo_map_error.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                    ctypes.c_void_p, ctypes.c_void_p]
@@ -302,13 +310,14 @@ def vcm_eval_pruned(scene, query, method: int, theta: int = 1,
     T, G, P = make_target(query.target), make_grid(g), make_params(query.params)
     out = {"count": np.zeros(n, dtype=np.uint16), "c": np.zeros(n), "cb": np.zeros(n),
            "bin": np.zeros(n, dtype=np.uint8), "cell": np.zeros((n, 2), dtype=np.int32),
-           "t_fallback": np.zeros(n, dtype=np.uint8)}
+           "t_fallback": np.zeros(n, dtype=np.uint8), "decided": np.zeros(n, dtype=np.uint8)}
     r = _plib().vo_eval_pruned(int(scene.dim), int(scene.n), lo.ctypes.data, hi.ctypes.data,
                                ctypes.byref(T), ctypes.byref(G), ctypes.byref(P), int(method),
                                int(theta), vp.ctypes.data, n, int(nthreads),
                                out["count"].ctypes.data, out["c"].ctypes.data,
                                out["cb"].ctypes.data, out["bin"].ctypes.data,
-                               out["cell"].ctypes.data, out["t_fallback"].ctypes.data)
+                               out["cell"].ctypes.data, out["t_fallback"].ctypes.data,
+                               out["decided"].ctypes.data)
     if r != 0:
         raise ValueError("oracle rejected the pruned query")
     return out
@@ -321,3 +330,36 @@ def map_error(c_exact, c_approx):
     _plib().vo_map_error(ce.ctypes.data, ca.ctypes.data, len(ce), ctypes.addressof(s),
                          ctypes.addressof(a))
     return s.value, a.value
+
+
+# ------------------------------------------------------------ blocks -------
+
+def hull_meets_box(L, H, s, a, c, dim=3) -> bool:
+    """Does the closed box [a, c] meet the convex hull of the box [L, H] and
+    the point s?"""
+    L, H, s, a, c = (_vec3(v) for v in (L, H, s, a, c))
+    r = _plib().vo_hull_meets_box(int(dim), L.ctypes.data, H.ctypes.data, s.ctypes.data,
+                                  a.ctypes.data, c.ctypes.data)
+    if r < 0:
+        raise ValueError("inputs must be multiples of 2^-8 with lo <= hi")
+    return bool(r)
+
+
+def classify_block(scene, query, lo_idx, hi_idx):
+    """Whole-block classification of the viewpoints with grid indices
+    lo_idx .. hi_idx (inclusive): None if undecided, else (count, N, in_fov)
+    shared by every viewpoint of the block."""
+    lo = np.ascontiguousarray(scene.lo, dtype=np.float64)
+    hi = np.ascontiguousarray(scene.hi, dtype=np.float64)
+    T, G, P = make_target(query.target), make_grid(query.grid), make_params(query.params)
+    il = np.zeros(3, dtype=np.int64)
+    ih = np.zeros(3, dtype=np.int64)
+    il[:len(lo_idx)] = lo_idx
+    ih[:len(hi_idx)] = hi_idx
+    out = np.zeros(3, dtype=np.int32)
+    r = _plib().vo_classify_block(int(scene.dim), int(scene.n), lo.ctypes.data, hi.ctypes.data,
+                                  ctypes.byref(T), ctypes.byref(G), ctypes.byref(P), il.ctypes.data,
+                                  ih.ctypes.data, out.ctypes.data)
+    if r < 0:
+        raise ValueError("invalid block or query")
+    return (int(out[0]), int(out[1]), int(out[2])) if r else None

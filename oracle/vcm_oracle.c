@@ -21,6 +21,10 @@
  *     V = 2 arctan(S_alpha / 2D), S_alpha = (alpha / 90 deg) S.
  *   - Field of view (Sec. III-B): viewpoints outside the FOV wedge around the
  *     target normal are obstructed.
+ *   - Pruned construction: equi-visible cells (Sec. III-A), visible-region
+ *     blocks split down to a minimum size (Sec. III-C-1), the MBR and
+ *     tangential approximations and their error bounds (Sec. IV-A), the
+ *     error measure (Sec. V-A).
  *
  * Readings taken where the paper is silent:
  *   - S is the largest target dimension; D is the distance from the viewpoint
@@ -466,6 +470,43 @@ static void target_box(const vo_target *t, double *lo, double *hi)
     }
 }
 
+/* Boxes in quanta, [box][3] (zeros beyond dim), in *blo_out / *bhi_out
+ * (to be freed).  -1 if a coordinate is off the lattice, a box has lo > hi,
+ * or a box meets the target's box: the target is not an obstacle (Def. 2.1
+ * keeps them apart), so such a query is rejected. */
+static int load_boxes(int dim, int64_t nbox, const double *lo, const double *hi, const vo_target *t,
+                      int64_t **blo_out, int64_t **bhi_out)
+{
+    int64_t *blo = (int64_t *)calloc((size_t)(nbox > 0 ? nbox : 1) * 3, sizeof(int64_t));
+    int64_t *bhi = (int64_t *)calloc((size_t)(nbox > 0 ? nbox : 1) * 3, sizeof(int64_t));
+    int bad = 0;
+    for (int64_t b = 0; b < nbox && !bad; ++b)
+        for (int a = 0; a < dim; ++a)
+            if (to_quanta(lo[a * nbox + b], &blo[3 * b + a]) || to_quanta(hi[a * nbox + b], &bhi[3 * b + a]) ||
+                blo[3 * b + a] > bhi[3 * b + a])
+                bad = 1;
+    double tl[3], th[3];
+    int64_t TL[3] = {0, 0, 0}, TH[3] = {0, 0, 0};
+    target_box(t, tl, th);
+    for (int a = 0; a < dim && !bad; ++a)
+        if (to_quanta(tl[a], &TL[a]) || to_quanta(th[a], &TH[a]))
+            bad = 1;
+    for (int64_t b = 0; b < nbox && !bad; ++b) {
+        int meet = 1;
+        for (int a = 0; a < dim; ++a)
+            meet = meet && blo[3 * b + a] <= TH[a] && bhi[3 * b + a] >= TL[a];
+        bad = meet;
+    }
+    if (bad) {
+        free(blo);
+        free(bhi);
+        return -1;
+    }
+    *blo_out = blo;
+    *bhi_out = bhi;
+    return 0;
+}
+
 /* Evaluate the VCM at the listed viewpoints (linear index, x fastest).
  * lo/hi: [3][nbox] SoA, multiples of 2^-8.  Any output pointer may be NULL.
  * count: FRACTION mode: visible live samples; FULL mode: N(q) when all are
@@ -479,41 +520,9 @@ int vo_eval(int dim, int64_t nbox, const double *lo, const double *hi,
 {
     if (check_query(dim, t, g, p))
         return -1;
-    int64_t *blo = (int64_t *)calloc((size_t)(nbox > 0 ? nbox : 1) * 3, sizeof(int64_t));
-    int64_t *bhi = (int64_t *)calloc((size_t)(nbox > 0 ? nbox : 1) * 3, sizeof(int64_t));
-    for (int64_t b = 0; b < nbox; ++b)
-        for (int a = 0; a < dim; ++a) {
-            if (to_quanta(lo[a * nbox + b], &blo[3 * b + a]) ||
-                to_quanta(hi[a * nbox + b], &bhi[3 * b + a]) ||
-                blo[3 * b + a] > bhi[3 * b + a]) {
-                free(blo);
-                free(bhi);
-                return -1;
-            }
-        }
-    /* The target is not an obstacle (Def. 2.1 keeps them apart): a query
-     * whose target box meets a closed obstacle box is rejected. */
-    {
-        double tl[3], th[3];
-        int64_t TL[3] = {0, 0, 0}, TH[3] = {0, 0, 0};
-        target_box(t, tl, th);
-        for (int a = 0; a < dim; ++a)
-            if (to_quanta(tl[a], &TL[a]) || to_quanta(th[a], &TH[a])) {
-                free(blo);
-                free(bhi);
-                return -1;
-            }
-        for (int64_t b = 0; b < nbox; ++b) {
-            int meet = 1;
-            for (int a = 0; a < dim; ++a)
-                meet = meet && blo[3 * b + a] <= TH[a] && bhi[3 * b + a] >= TL[a];
-            if (meet) {
-                free(blo);
-                free(bhi);
-                return -1;
-            }
-        }
-    }
+    int64_t *blo, *bhi;
+    if (load_boxes(dim, nbox, lo, hi, t, &blo, &bhi))
+        return -1;
     if (nthreads < 1)
         nthreads = 1;
     if (nthreads > 256)
@@ -786,48 +795,374 @@ void vo_meridian(const vo_target *t, const double *q, double *out)
     meridian(t, q, &out[0], &out[1]);
 }
 
-/* Representative viewpoint of q for a minimum block size theta: the grid is
- * cut into aligned blocks of theta viewpoints per axis and every viewpoint
- * takes the visibility of its block's lowest-index centre viewpoint (Sec.
- * III-C, blocks not split below theta; the baseline of Sec. V-B likewise
- * uses one point per grid cell).  theta = 1 gives q itself. */
-int64_t vo_block_rep(const vo_grid *g, int dim, int theta, int64_t idx)
+/* ===================================================================== */
+/* Visible-region blocks (Sec. III-C-1, "Indexing Visible Regions"): a    */
+/* block of viewpoints is decided when the target is seen completely from  */
+/* all of it or from none of it; otherwise it is split, down to the        */
+/* minimum block size.                                                     */
+/* ===================================================================== */
+
+/* Does the closed box [a, c] meet the convex hull of the box [L, H] and the
+ * point s?  That hull is the union over lambda in [0, 1] of the boxes
+ * [s + lambda (L - s), s + lambda (H - s)], so the box meets it iff some
+ * lambda in [0, 1] satisfies, along every axis k,
+ *   s_k + lambda (L_k - s_k) <= c_k   and   s_k + lambda (H_k - s_k) >= a_k,
+ * each a bound on lambda of the form lambda x <= y.  Bounds are fractions
+ * compared by cross-multiplication: exact in quanta. */
+static int hull_meets_box(int dim, const int64_t *L, const int64_t *H, const int64_t *s,
+                          const int64_t *a, const int64_t *c)
+{
+    int64_t ln = 0, ld = 1, un = 1, ud = 1; /* lambda in [ln/ld, un/ud] */
+    for (int k = 0; k < dim; ++k)
+        for (int side = 0; side < 2; ++side) {
+            int64_t x = side ? s[k] - H[k] : L[k] - s[k];
+            int64_t y = side ? s[k] - a[k] : c[k] - s[k];
+            if (x > 0) {
+                if (y * ud < un * x) { /* lambda <= y / x is tighter */
+                    un = y;
+                    ud = x;
+                }
+            } else if (x < 0) {
+                if (-y * ld > ln * -x) { /* lambda >= (-y) / (-x) is tighter */
+                    ln = -y;
+                    ld = -x;
+                }
+            } else if (y < 0) {
+                return 0;
+            }
+        }
+    return ln * ud <= un * ld;
+}
+
+/* Field of view over a box of viewpoints given by its corners: 1 if every
+ * viewpoint of the box is inside, 0 if every one is outside, -1 if that
+ * cannot be told from the corners.  A set that is convex contains the box
+ * when it contains the corners: the wedge itself when it is no wider than a
+ * half-space, else the half-space in front of the target; the half-space
+ * behind the target, else the complement of a wide wedge (a convex cone). */
+static int fov_class(const vo_target *t, const vo_params *p, int nc, const double (*cq)[3])
+{
+    double half = p->fov_deg / 2.0;
+    if (half >= 180.0)
+        return 1;
+    int all_in = 1, all_out = 1, all_front = 1, all_back = 1;
+    for (int c = 0; c < nc; ++c) {
+        int in = vo_in_fov(t, p, cq[c]);
+        double dn = t->normal_sign * (cq[c][t->normal_axis] - t->center[t->normal_axis]);
+        all_in = all_in && in;
+        all_out = all_out && !in;
+        all_front = all_front && dn >= 0.0;
+        all_back = all_back && dn < 0.0;
+    }
+    if (half <= 90.0)
+        return all_in ? 1 : (all_back ? 0 : -1);
+    return all_front ? 1 : (all_out ? 0 : -1);
+}
+
+/* Classify the block of viewpoints with grid indices lo[a] .. hi[a]
+ * (inclusive) as a whole.  Its viewpoints lie in the box spanned by the
+ * block's extreme viewpoints; C denotes that box.
+ *   - The live samples and the field of view must be the same for all of C
+ *     (each live-face condition is a half-space; the field of view by
+ *     fov_class), else the block is undecided.
+ *   - Outside the field of view, or with no live sample: decided, count 0.
+ *   - A live sample s is seen from all of C when no obstacle meets the
+ *     convex hull of C and s (every line of sight lies in it); it is hidden
+ *     from all of C when one obstacle o meets the segments from every
+ *     corner of C to s (the points whose segment to s meets o form a convex
+ *     set, so it holds C).
+ *   - FULL mode: some live sample hidden from all of C: decided, count 0;
+ *     every live sample seen from all of C: decided, count N; else
+ *     undecided.
+ *   - FRACTION mode: every live sample either seen from or hidden from all
+ *     of C: decided, count = the samples seen; else undecided.
+ * A decided block gives every one of its viewpoints the count, live count
+ * and field of view the brute force gives it.  Returns 1 (decided) with
+ * out = {count, N, in FOV}, else 0.  Boxes in quanta, [box][3]. */
+static int classify_block(int dim, int64_t nbox, const int64_t *blo, const int64_t *bhi,
+                          const vo_target *t, const vo_grid *g, const vo_params *p,
+                          const int64_t *lo, const int64_t *hi, int *out)
+{
+    int nc = 1 << dim;
+    double cq[8][3];
+    int64_t CQ[8][3], L[3] = {0, 0, 0}, H[3] = {0, 0, 0};
+    for (int c = 0; c < nc; ++c)
+        for (int a = 0; a < 3; ++a) {
+            cq[c][a] = 0.0;
+            CQ[c][a] = 0;
+            if (a < dim) {
+                int64_t i = ((c >> a) & 1) ? hi[a] : lo[a];
+                cq[c][a] = g->origin[a] + (double)(2 * i + 1) * (g->extent[a] / (2.0 * (double)g->n[a]));
+                to_quanta(cq[c][a], &CQ[c][a]);
+            }
+        }
+    for (int a = 0; a < dim; ++a) {
+        L[a] = CQ[0][a];
+        H[a] = CQ[nc - 1][a];
+    }
+    /* live samples: the same set at every corner */
+    int maxs = 6 * t->su * t->sv;
+    double *smp = (double *)malloc(sizeof(double) * 3 * (size_t)maxs);
+    double *tmp = (double *)malloc(sizeof(double) * 3 * (size_t)maxs);
+    int n = vo_live_samples(t, cq[0], smp);
+    int uniform = 1;
+    for (int c = 1; c < nc && uniform; ++c) {
+        int m = vo_live_samples(t, cq[c], tmp);
+        uniform = m == n && memcmp(smp, tmp, sizeof(double) * 3 * (size_t)n) == 0;
+    }
+    free(tmp);
+    int fc = fov_class(t, p, nc, cq);
+    if (!uniform || fc < 0) {
+        free(smp);
+        return 0;
+    }
+    out[1] = n;
+    out[2] = fc;
+    if (fc == 0 || n == 0) {
+        out[0] = 0;
+        free(smp);
+        return 1;
+    }
+    int seen = 0, hidden = 0;
+    for (int s = 0; s < n; ++s) {
+        int64_t S[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a)
+            to_quanta(smp[3 * s + a], &S[a]);
+        int vis = 1, hid = 0;
+        for (int64_t b = 0; b < nbox && !hid; ++b) {
+            if (!hull_meets_box(dim, L, H, S, &blo[3 * b], &bhi[3 * b]))
+                continue;
+            vis = 0;
+            int all = 1;
+            for (int c = 0; c < nc && all; ++c)
+                all = seg_meets_box(dim, CQ[c], S, &blo[3 * b], &bhi[3 * b]);
+            hid = all;
+        }
+        seen += vis;
+        hidden += hid;
+        if (p->mode == VO_FULL && hid)
+            break;
+    }
+    free(smp);
+    if (p->mode == VO_FULL) {
+        if (hidden) {
+            out[0] = 0;
+            return 1;
+        }
+        if (seen == n) {
+            out[0] = n;
+            return 1;
+        }
+        return 0;
+    }
+    if (seen + hidden == n) {
+        out[0] = seen;
+        return 1;
+    }
+    return 0;
+}
+
+/* Side of the smallest blocks for a minimum block size theta (viewpoints):
+ * blocks are halved, so it is the largest power of two not above theta. */
+static int64_t leaf_side(int theta)
+{
+    int64_t s = 1;
+    while (2 * s <= theta)
+        s *= 2;
+    return s;
+}
+
+/* The smallest block holding viewpoint idx: aligned blocks of `side`
+ * viewpoints per axis, cut by the grid's end; its index ranges and its
+ * representative, the lowest-index viewpoint of its centre. */
+static void leaf_block(const vo_grid *g, int dim, int64_t side, int64_t idx, int64_t *lo, int64_t *hi,
+                       int64_t *rep, int64_t *key)
 {
     int64_t ii[3] = {idx % g->n[0], (idx / g->n[0]) % g->n[1], idx / (g->n[0] * g->n[1])};
-    for (int a = 0; a < dim; ++a) {
-        int64_t b0 = (ii[a] / theta) * theta;
-        int64_t off = (theta - 1) / 2;
-        if (b0 + off > g->n[a] - 1)
-            off = g->n[a] - 1 - b0;
-        ii[a] = b0 + off;
+    int64_t r[3] = {0, 0, 0}, b[3] = {0, 0, 0}, nb[3] = {1, 1, 1};
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = hi[a] = 0;
+        if (a >= dim)
+            continue;
+        b[a] = ii[a] / side;
+        nb[a] = (g->n[a] + side - 1) / side;
+        lo[a] = b[a] * side;
+        hi[a] = lo[a] + side - 1 < g->n[a] - 1 ? lo[a] + side - 1 : g->n[a] - 1;
+        int64_t off = (side - 1) / 2;
+        r[a] = lo[a] + (off < hi[a] - lo[a] ? off : hi[a] - lo[a]);
     }
-    return ii[0] + g->n[0] * (ii[1] + g->n[1] * ii[2]);
+    *rep = r[0] + g->n[0] * (r[1] + g->n[1] * r[2]);
+    *key = b[0] + nb[0] * (b[1] + nb[1] * b[2]);
+}
+
+/* Public wrappers (pins).  vo_hull_meets_box: 1 if the closed box [a, c]
+ * meets the convex hull of the box [L, H] and the point s, 0 if not, -1 on
+ * input off the lattice. */
+int vo_hull_meets_box(int dim, const double *L, const double *H, const double *s, const double *a,
+                      const double *c)
+{
+    int64_t l[3] = {0, 0, 0}, h[3] = {0, 0, 0}, S[3] = {0, 0, 0}, A[3] = {0, 0, 0}, C[3] = {0, 0, 0};
+    for (int k = 0; k < dim; ++k)
+        if (to_quanta(L[k], &l[k]) || to_quanta(H[k], &h[k]) || to_quanta(s[k], &S[k]) ||
+            to_quanta(a[k], &A[k]) || to_quanta(c[k], &C[k]) || l[k] > h[k] || A[k] > C[k])
+            return -1;
+    return hull_meets_box(dim, l, h, S, A, C);
+}
+
+/* vo_classify_block: the classification of the block of viewpoints with
+ * grid indices lo[a] .. hi[a]: 1 (decided, out = {count, N, in FOV}),
+ * 0 (undecided), -1 (invalid input). */
+int vo_classify_block(int dim, int64_t nbox, const double *lo, const double *hi, const vo_target *t,
+                      const vo_grid *g, const vo_params *p, const int64_t *ilo, const int64_t *ihi, int *out)
+{
+    if (check_query(dim, t, g, p))
+        return -1;
+    for (int a = 0; a < dim; ++a)
+        if (ilo[a] < 0 || ihi[a] < ilo[a] || ihi[a] >= g->n[a])
+            return -1;
+    int64_t *blo, *bhi;
+    if (load_boxes(dim, nbox, lo, hi, t, &blo, &bhi))
+        return -1;
+    int r = classify_block(dim, nbox, blo, bhi, t, g, p, ilo, ihi, out);
+    free(blo);
+    free(bhi);
+    return r;
+}
+
+/* Representative viewpoint of q for a minimum block size theta: the
+ * lowest-index centre viewpoint of q's smallest block (side: the largest
+ * power of two not above theta; cut by the grid's end).  A smallest block
+ * that is not decided takes its representative's visibility (Sec. III-C-1
+ * stops splitting there; the baseline of Sec. V-B likewise uses one point
+ * per grid cell).  theta = 1 gives q itself. */
+int64_t vo_block_rep(const vo_grid *g, int dim, int theta, int64_t idx)
+{
+    int64_t lo[3], hi[3], rep, key;
+    leaf_block(g, dim, leaf_side(theta), idx, lo, hi, &rep, &key);
+    return rep;
+}
+
+typedef struct {
+    int dim;
+    int64_t nbox;
+    const int64_t *blo, *bhi;
+    const vo_target *t;
+    const vo_grid *g;
+    const vo_params *p;
+    int64_t side;
+    const int64_t *leaf_vp; /* one viewpoint of each leaf */
+    int *decided, *gate;    /* per leaf: decided, {count, N, in FOV} */
+    int64_t first, last;
+} vo_leaf_job;
+
+static void *classify_thread(void *arg)
+{
+    vo_leaf_job *J = (vo_leaf_job *)arg;
+    for (int64_t u = J->first; u < J->last; ++u) {
+        int64_t lo[3], hi[3], rep, key;
+        leaf_block(J->g, J->dim, J->side, J->leaf_vp[u], lo, hi, &rep, &key);
+        J->decided[u] = classify_block(J->dim, J->nbox, J->blo, J->bhi, J->t, J->g, J->p, lo, hi, &J->gate[3 * u]);
+    }
+    return NULL;
+}
+
+typedef struct {
+    int64_t key, v;
+} vo_keyed;
+
+static int cmp_keyed(const void *a, const void *b)
+{
+    const vo_keyed *x = (const vo_keyed *)a, *y = (const vo_keyed *)b;
+    if (x->key != y->key)
+        return x->key < y->key ? -1 : 1;
+    return x->v < y->v ? -1 : (x->v > y->v);
 }
 
 /* Pruned VCM at the listed viewpoints: method 1 = E, 2 = M, 3 = T.
- * The gate (visible count and N(q), FOV) comes from the brute-force oracle
- * at the block representative; the colour from the cell lookups at q.
- * count/c/cb/bin as in vo_eval; cell_out: ring, band of q's own cell. */
+ * The gate (visible count, N(q), FOV) of q comes from q's smallest block
+ * (side: the largest power of two not above theta): if that block is
+ * decided as a whole (classify_block), its count; otherwise the brute-force
+ * oracle at the block's representative.  (A block that is decided keeps
+ * every sub-block decided, so the blocks above the smallest ones do not
+ * change the map: the quad-/oct-tree only saves work.)  The colour comes
+ * from the cell lookups at q.  count/c/cb/bin as in vo_eval; cell_out:
+ * ring, band of q's own cell; decided_out: 1 where q's block was decided. */
 int vo_eval_pruned(int dim, int64_t nbox, const double *lo, const double *hi,
                    const vo_target *t, const vo_grid *g, const vo_params *p,
                    int method, int theta, const int64_t *vp, int64_t nvp, int nthreads,
                    uint16_t *count, double *c, double *cb, uint8_t *bin, int32_t *cell_out,
-                   uint8_t *t_fallback)
+                   uint8_t *t_fallback, uint8_t *decided_out)
 {
     if (method < 1 || method > 3 || theta < 1)
         return -1;
+    if (check_query(dim, t, g, p))
+        return -1;
+    int64_t *blo, *bhi;
+    if (load_boxes(dim, nbox, lo, hi, t, &blo, &bhi))
+        return -1;
     vo_cells cells;
     double mu = p->mu_arcmin * VO_PI / (180.0 * 60.0);
-    if (vo_partition(target_size(t), mu, p->d0, &cells))
+    if (vo_partition(target_size(t), mu, p->d0, &cells)) {
+        free(blo);
+        free(bhi);
         return -1;
-    int64_t *rep = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nvp > 0 ? nvp : 1));
+    }
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    int64_t side = leaf_side(theta);
+    size_t nv = (size_t)(nvp > 0 ? nvp : 1);
+    /* the smallest block of every viewpoint, each distinct block once */
+    vo_keyed *kv = (vo_keyed *)malloc(sizeof(vo_keyed) * nv);
+    int64_t *rep_of = (int64_t *)malloc(sizeof(int64_t) * nv);
+    for (int64_t v = 0; v < nvp; ++v) {
+        int64_t l[3], h[3];
+        leaf_block(g, dim, side, vp[v], l, h, &rep_of[v], &kv[v].key);
+        kv[v].v = v;
+    }
+    qsort(kv, (size_t)nvp, sizeof(vo_keyed), cmp_keyed);
+    int64_t *leaf_of = (int64_t *)malloc(sizeof(int64_t) * nv); /* viewpoint -> distinct block */
+    int64_t *leaf_vp = (int64_t *)malloc(sizeof(int64_t) * nv);
+    int64_t nleaf = 0;
+    for (int64_t k = 0; k < nvp; ++k) {
+        if (k == 0 || kv[k].key != kv[k - 1].key)
+            leaf_vp[nleaf++] = vp[kv[k].v];
+        leaf_of[kv[k].v] = nleaf - 1;
+    }
+    int *decided = (int *)calloc((size_t)(nleaf > 0 ? nleaf : 1), sizeof(int));
+    int *lgate = (int *)calloc((size_t)(nleaf > 0 ? nleaf : 1) * 3, sizeof(int));
+    {
+        vo_leaf_job base = {dim, nbox, blo, bhi, t, g, p, side, leaf_vp, decided, lgate, 0, nleaf};
+        vo_leaf_job jobs[256];
+        pthread_t th[256];
+        int nt = nleaf < nthreads ? (int)(nleaf > 0 ? nleaf : 1) : nthreads;
+        for (int i = 0; i < nt; ++i) {
+            jobs[i] = base;
+            jobs[i].first = nleaf * i / nt;
+            jobs[i].last = nleaf * (i + 1) / nt;
+            if (nt == 1)
+                classify_thread(&jobs[i]);
+            else
+                pthread_create(&th[i], NULL, classify_thread, &jobs[i]);
+        }
+        if (nt > 1)
+            for (int i = 0; i < nt; ++i)
+                pthread_join(th[i], NULL);
+    }
+    /* representatives of the undecided blocks, by the brute-force oracle */
+    int64_t *reps = (int64_t *)malloc(sizeof(int64_t) * nv);
+    int64_t nrep = 0;
     for (int64_t v = 0; v < nvp; ++v)
-        rep[v] = vo_block_rep(g, dim, theta, vp[v]);
-    uint16_t *rc = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)(nvp > 0 ? nvp : 1));
-    uint16_t *rn = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)(nvp > 0 ? nvp : 1));
-    uint8_t *rf = (uint8_t *)malloc((size_t)(nvp > 0 ? nvp : 1));
-    int r = vo_eval(dim, nbox, lo, hi, t, g, p, rep, nvp, nthreads, rc, rn, rf, NULL, NULL, NULL);
+        if (!decided[leaf_of[v]])
+            reps[nrep++] = rep_of[v];
+    size_t nr = (size_t)(nrep > 0 ? nrep : 1);
+    uint16_t *rc = (uint16_t *)malloc(sizeof(uint16_t) * nr);
+    uint16_t *rn = (uint16_t *)malloc(sizeof(uint16_t) * nr);
+    uint8_t *rf = (uint8_t *)malloc(nr);
+    int r = nrep > 0 ? vo_eval(dim, nbox, lo, hi, t, g, p, reps, nrep, nthreads, rc, rn, rf, NULL, NULL, NULL) : 0;
     if (r == 0) {
+        int64_t k = 0;
         for (int64_t v = 0; v < nvp; ++v) {
             int64_t idx = vp[v];
             int64_t ii[3] = {idx % g->n[0], (idx / g->n[0]) % g->n[1], idx / (g->n[0] * g->n[1])};
@@ -839,10 +1174,20 @@ int vo_eval_pruned(int dim, int64_t nbox, const double *lo, const double *hi,
             meridian(t, q, &D, &al);
             vo_pruned_colours(&cells, D, al, cols, cl, &tf);
             double craw = cols[method - 1];
-            int n = rn[v], vis = rc[v];
+            int u = (int)leaf_of[v];
+            int vis, n, inf;
+            if (decided[u]) {
+                vis = lgate[3 * u];
+                n = lgate[3 * u + 1];
+                inf = lgate[3 * u + 2];
+            } else {
+                vis = rc[k];
+                n = rn[k];
+                inf = rf[k];
+                ++k;
+            }
             double col;
-            int cnt = vis;
-            if (!rf[v] || n == 0)
+            if (!inf || n == 0)
                 col = 0.0;
             else if (p->mode == VO_FRACTION)
                 col = ((double)vis / (double)n) * craw;
@@ -851,7 +1196,7 @@ int vo_eval_pruned(int dim, int64_t nbox, const double *lo, const double *hi,
             double cbv;
             uint8_t bn;
             to_bin(p, col, cells.V0, &cbv, &bn);
-            if (count) count[v] = (uint16_t)cnt;
+            if (count) count[v] = (uint16_t)vis;
             if (c) c[v] = col;
             if (cb) cb[v] = cbv;
             if (bin) bin[v] = bn;
@@ -860,12 +1205,21 @@ int vo_eval_pruned(int dim, int64_t nbox, const double *lo, const double *hi,
                 cell_out[2 * v + 1] = cl[1];
             }
             if (t_fallback) t_fallback[v] = (uint8_t)tf;
+            if (decided_out) decided_out[v] = (uint8_t)decided[u];
         }
     }
-    free(rep);
+    free(kv);
+    free(rep_of);
+    free(leaf_of);
+    free(leaf_vp);
+    free(decided);
+    free(lgate);
+    free(reps);
     free(rc);
     free(rn);
     free(rf);
+    free(blo);
+    free(bhi);
     vo_free_cells(&cells);
     return r;
 }

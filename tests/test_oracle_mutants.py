@@ -67,6 +67,24 @@ MUTANTS = [
      "    for (int i = 0; i < c->nring; ++i) {\n        int j = band_of(c, i, alpha);",
      "    for (int i = c->nring - 1; i >= 0; --i) {\n        int j = band_of(c, i, alpha);",
      [P + "test_t_takes_the_lowest_ring_whose_tangent_trapezoid_holds_q"]),
+    ("hull test keeps the looser lower bound of lambda",
+     "                if (-y * ld > ln * -x) {", "                if (-y * ld < ln * -x) {",
+     ["tests/test_oracle_blocks.py::test_hull_of_a_point_block_is_the_segment_test",
+      "tests/test_oracle_blocks.py::test_hull_test_matches_a_linear_program"]),
+    ("a sample counts as hidden when one corner's segment is cut",
+     "            for (int c = 0; c < nc && all; ++c)", "            for (int c = 0; c < 1 && all; ++c)",
+     ["tests/test_oracle_blocks.py::test_decided_blocks_agree_with_brute_force_everywhere"]),
+    ("wide field of view taken as convex",
+     "    return all_front ? 1 : (all_out ? 0 : -1);", "    return all_in ? 1 : (all_out ? 0 : -1);",
+     ["tests/test_oracle_blocks.py::test_block_hand_cases"]),
+    ("live faces not checked for the whole block",
+     "        uniform = m == n && memcmp(smp, tmp, sizeof(double) * 3 * (size_t)n) == 0;",
+     "        uniform = 1;",
+     ["tests/test_oracle_blocks.py::test_decided_blocks_agree_with_brute_force_everywhere",
+      "tests/test_oracle_blocks.py::test_block_hand_cases"]),
+    ("FRACTION-mode block decided with one sample undecided",
+     "    if (seen + hidden == n) {", "    if (seen + hidden >= n - 1) {",
+     ["tests/test_oracle_blocks.py::test_decided_blocks_agree_with_brute_force_everywhere"]),
     ("error bounds count the bands above the stated angle",
      "                if (g[j + 1] < lim[m])", "                if (g[j + 1] > lim[m])",
      [P + "test_measured_error_within_the_printed_bounds"]),

@@ -151,14 +151,18 @@ def test_error_bounds_order(cells30):
 
 
 def test_block_representative():
+    """Smallest blocks have the largest power-of-two side not above theta
+    (blocks are halved), are aligned, are cut by the grid's end, and are
+    represented by their lowest-index centre viewpoint."""
     g = Grid((0.0, 0.0, 0.0), (10.0, 10.0, 10.0), (5, 5, 5))
     idx = lambda i, j, k: i + 5 * (j + 5 * k)
     for i in range(5):
         assert oracle.block_rep(g, 3, 1, idx(i, 2, 3)) == idx(i, 2, 3)
     assert oracle.block_rep(g, 3, 2, idx(1, 2, 3)) == idx(0, 2, 2)
-    assert oracle.block_rep(g, 3, 3, idx(1, 2, 3)) == idx(1, 1, 4)
+    assert oracle.block_rep(g, 3, 3, idx(1, 2, 3)) == idx(0, 2, 2)   # side 2
     assert oracle.block_rep(g, 3, 4, idx(4, 4, 4)) == idx(4, 4, 4)   # ragged block
     assert oracle.block_rep(g, 3, 4, idx(3, 0, 2)) == idx(1, 1, 1)
+    assert oracle.block_rep(g, 3, 7, idx(3, 0, 2)) == idx(1, 1, 1)   # side 4
 
 
 def test_pruned_gate_equals_brute_at_theta_one():
