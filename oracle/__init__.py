@@ -188,7 +188,7 @@ class VoCells(ctypes.Structure):
     _fields_ = [("nring", ctypes.c_int), ("d", ctypes.POINTER(ctypes.c_double)),
                 ("boff", ctypes.POINTER(ctypes.c_int64)), ("gam", ctypes.POINTER(ctypes.c_double)),
                 ("S", ctypes.c_double), ("mu", ctypes.c_double), ("d0", ctypes.c_double),
-                ("V0", ctypes.c_double)]
+                ("V0", ctypes.c_double), ("rings_only", ctypes.c_int)]
 
 
 def _plib():
@@ -197,6 +197,8 @@ def _plib():
         L.vo_partition.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                    ctypes.POINTER(VoCells)]
         L.vo_partition.restype = ctypes.c_int
+        L.vo_partition_rings.argtypes = L.vo_partition.argtypes
+        L.vo_partition_rings.restype = ctypes.c_int
         L.vo_free_cells.argtypes = [ctypes.POINTER(VoCells)]
         L.vo_cells_size.argtypes = [ctypes.POINTER(VoCells), ctypes.POINTER(ctypes.c_int64)]
         L.vo_cells_size.restype = ctypes.c_int
@@ -234,9 +236,10 @@ def _plib():
 class Cells:
     """Equi-visible cells (rings x bands) of a target of size S."""
 
-    def __init__(self, S: float, mu_rad: float, d0: float):
+    def __init__(self, S: float, mu_rad: float, d0: float, rings_only: bool = False):
         self._c = VoCells()
-        if _plib().vo_partition(float(S), float(mu_rad), float(d0), ctypes.byref(self._c)):
+        part = _plib().vo_partition_rings if rings_only else _plib().vo_partition
+        if part(float(S), float(mu_rad), float(d0), ctypes.byref(self._c)):
             raise ValueError("invalid partition parameters")
         nb = ctypes.c_int64()
         nr = _plib().vo_cells_size(ctypes.byref(self._c), ctypes.byref(nb))

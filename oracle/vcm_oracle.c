@@ -21,6 +21,11 @@
  *     V = 2 arctan(S_alpha / 2D), S_alpha = (alpha / 90 deg) S.
  *   - Field of view (Sec. III-B): viewpoints outside the FOV wedge around the
  *     target normal are obstructed.
+ *   - Viewer-centric VCM (Sec. IV-B): a viewer q instead of a target; the map
+ *     covers the ball of radius d_max about q, and S is the size whose visual
+ *     angle is mu at d_max, S = 2 d_max tan(mu / 2).  Read as a point target
+ *     at q of that size, seen facing (no foreshortening), by the symmetry of
+ *     visibility (Sec. III-A).
  *   - Pruned construction: equi-visible cells (Sec. III-A), visible-region
  *     blocks split down to a minimum size (Sec. III-C-1), the MBR and
  *     tangential approximations and their error bounds (Sec. IV-A), the
@@ -52,7 +57,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { VO_SEGMENT = 0, VO_BILLBOARD = 1, VO_CUBE = 2 };
+enum { VO_SEGMENT = 0, VO_BILLBOARD = 1, VO_CUBE = 2, VO_VIEWER = 3 };
 enum { VO_FULL = 0, VO_FRACTION = 1 };
 enum { VO_BIN_LINEAR = 0, VO_BIN_LOG = 1 };
 
@@ -158,10 +163,17 @@ int vo_segment_meets_box(int dim, const double *q, const double *s,
 
 /* --------------------------------------------------------- target side -- */
 
-static double target_size(const vo_target *t)
+static double mu_rad(const vo_params *p) { return p->mu_arcmin * VO_PI / (180.0 * 60.0); }
+
+/* Size S entering Eq. 1: the largest target dimension; for the viewer of a
+ * viewer-centric map (size[0] = d_max), the size whose visual angle at d_max
+ * is mu (Sec. IV-B): 2 arctan(S / (2 d_max)) = mu. */
+static double target_size(const vo_target *t, const vo_params *p)
 {
     if (t->kind == VO_BILLBOARD)
         return t->size[0] > t->size[1] ? t->size[0] : t->size[1];
+    if (t->kind == VO_VIEWER)
+        return 2.0 * t->size[0] * tan(mu_rad(p) / 2.0);
     return t->size[0];
 }
 
@@ -175,6 +187,14 @@ int vo_live_samples(const vo_target *t, const double *q, double *out)
 {
     int n = 0;
     const double *c = t->center;
+    if (t->kind == VO_VIEWER) {
+        if (out) {
+            out[0] = c[0];
+            out[1] = c[1];
+            out[2] = c[2];
+        }
+        return 1;
+    }
     if (t->kind == VO_SEGMENT || t->kind == VO_BILLBOARD) {
         int a = t->normal_axis;
         int w = 1 - a;
@@ -251,7 +271,9 @@ void vo_measure(const vo_target *t, const vo_params *p, const double *q, double 
     double rho = sqrt(r2);
     double D = sqrt(r2 + h * h);
     double alpha = atan2(h, rho);                 /* 90 deg facing, 0 edge-on */
-    double S = target_size(t);
+    if (t->kind == VO_VIEWER)
+        alpha = VO_PI / 2.0;                      /* a point seen facing */
+    double S = target_size(t, p);
     double s_alpha = (alpha / (VO_PI / 2.0)) * S; /* Eq. 2 */
     double Dn = D > p->d0 ? D : p->d0;            /* no closer than the near point */
     double V = 2.0 * atan(s_alpha / (2.0 * Dn));  /* Eq. 1 */
@@ -271,7 +293,7 @@ void vo_measure(const vo_target *t, const vo_params *p, const double *q, double 
  * for the half-angles 30/45/60/120/135/150 degrees (the table's FOVs and 90 /
  * 270 degrees), which makes the comparison exact on the 2^-8 lattice: a point
  * on the wedge's boundary is inside. */
-int vo_in_fov(const vo_target *t, const vo_params *p, const double *q)
+static int in_wedge(const vo_target *t, const vo_params *p, const double *q)
 {
     double half = p->fov_deg / 2.0;
     if (half >= 180.0)
@@ -298,6 +320,26 @@ int vo_in_fov(const vo_target *t, const vo_params *p, const double *q)
     if (half < 90.0)
         return dn >= 0.0 && dn * dn >= c2 * d2;
     return dn >= 0.0 || dn * dn <= c2 * d2;
+}
+
+/* A viewer-centric map covers the closed ball of radius d_max about the
+ * viewer (Sec. IV-B); every other map covers the whole space.  Exact on the
+ * 2^-8 lattice. */
+static int in_region(const vo_target *t, const double *q)
+{
+    if (t->kind != VO_VIEWER)
+        return 1;
+    double r2 = 0.0;
+    for (int k = 0; k < 3; ++k)
+        r2 += (q[k] - t->center[k]) * (q[k] - t->center[k]);
+    return r2 <= t->size[0] * t->size[0];
+}
+
+/* Viewpoints outside the field of view, or outside the region a
+ * viewer-centric map covers, are obstructed. */
+int vo_in_fov(const vo_target *t, const vo_params *p, const double *q)
+{
+    return in_region(t, q) && in_wedge(t, p, q);
 }
 
 /* ----------------------------------------------------------- colour ------ */
@@ -425,7 +467,14 @@ static int check_query(int dim, const vo_target *t, const vo_grid *g, const vo_p
     if (dim != 2 && dim != 3) return -1;
     if (p->n_bins < 2 || p->n_bins > 256) return -1;
     if (t->su <= 0 || t->sv <= 0) return -1;
-    if ((t->kind == VO_SEGMENT) != (dim == 2)) return -1;
+    if (t->kind == VO_VIEWER) {
+        int64_t r;
+        if (t->su != 1 || t->sv != 1 || !(t->size[0] > 0.0) || to_quanta(t->size[0], &r)) return -1;
+        if (dim == 2 && t->center[2] != 0.0) return -1;
+        if (!(2.0 * atan(target_size(t, p) / (2.0 * p->d0)) > mu_rad(p))) return -1;
+    } else if ((t->kind == VO_SEGMENT) != (dim == 2)) {
+        return -1;
+    }
     if (t->kind != VO_CUBE && t->normal_axis != 0 && t->normal_axis != 1) return -1;
     if (t->kind == VO_CUBE && p->fov_deg < 360.0) return -1;
     if (!(p->fov_deg > 0.0 && p->fov_deg <= 360.0)) return -1;
@@ -457,7 +506,9 @@ static int check_query(int dim, const vo_target *t, const vo_grid *g, const vo_p
 static void target_box(const vo_target *t, double *lo, double *hi)
 {
     double half[3] = {0.0, 0.0, 0.0};
-    if (t->kind == VO_CUBE) {
+    if (t->kind == VO_VIEWER) {
+        /* a point */
+    } else if (t->kind == VO_CUBE) {
         half[0] = half[1] = half[2] = t->size[0] / 2.0;
     } else {
         half[1 - t->normal_axis] = t->size[0] / 2.0;
@@ -559,6 +610,7 @@ typedef struct {
     double *gam;        /* per ring: gamma_0 = pi/2 > gamma_1 > ... > gamma_{L+1} = 0 (radians);
                            band j of the ring is (gamma_{j+1}, gamma_j]                   */
     double S, mu, d0, V0;
+    int rings_only;     /* viewer-centric maps: one band per ring, colour facing */
 } vo_cells;
 
 /* Distance-based partition (Sec. III-A-1) followed by the angle-based
@@ -576,7 +628,7 @@ typedef struct {
  * angle of a perceived size S_j = 2 d' tan(W_j / 2), which Eq. 2 attributes
  * to the viewing angle gamma_j = 90 deg * S_j / S.  The band boundaries are
  * these angles, from 90 deg down, while W_j >= mu; the last band reaches 0. */
-int vo_partition(double S, double mu, double d0, vo_cells *out)
+static int partition(double S, double mu, double d0, int rings_only, vo_cells *out)
 {
     memset(out, 0, sizeof(*out));
     if (!(S > 0) || !(mu > 0) || !(d0 > 0))
@@ -615,7 +667,7 @@ int vo_partition(double S, double mu, double d0, vo_cells *out)
             gam = (double *)realloc(gam, sizeof(double) * (size_t)gcap);
         }
         gam[gn++] = VO_PI / 2.0;
-        for (int j = 1;; ++j) {
+        for (int j = 1; !rings_only; ++j) {
             double W = W0 - j * mu;
             if (W < mu)
                 break;
@@ -637,8 +689,17 @@ int vo_partition(double S, double mu, double d0, vo_cells *out)
     out->mu = mu;
     out->d0 = d0;
     out->V0 = V0;
+    out->rings_only = rings_only;
     return 0;
 }
+
+int vo_partition(double S, double mu, double d0, vo_cells *out) { return partition(S, mu, d0, 0, out); }
+
+/* The partition of a viewer-centric map (Sec. IV-B): a point seen facing
+ * has no viewing angle to tell apart, so its equi-visible cells are the
+ * distance rings of Sec. III-A-1 alone, one band from 90 degrees to 0 each,
+ * coloured by the facing visual angle at the ring's middle distance. */
+int vo_partition_rings(double S, double mu, double d0, vo_cells *out) { return partition(S, mu, d0, 1, out); }
 
 void vo_free_cells(vo_cells *c)
 {
@@ -670,6 +731,8 @@ static double cell_colour(const vo_cells *c, int i, int j)
     const double *g = c->gam + c->boff[i];
     double dp = 0.5 * (c->d[i] + c->d[i + 1]);
     double gm = 0.5 * (g[j] + g[j + 1]);
+    if (c->rings_only)
+        gm = VO_PI / 2.0;
     return vis_angle(c->S, dp, gm) / c->V0;
 }
 
@@ -842,21 +905,46 @@ static int hull_meets_box(int dim, const int64_t *L, const int64_t *H, const int
  * behind the target, else the complement of a wide wedge (a convex cone). */
 static int fov_class(const vo_target *t, const vo_params *p, int nc, const double (*cq)[3])
 {
-    double half = p->fov_deg / 2.0;
-    if (half >= 180.0)
-        return 1;
-    int all_in = 1, all_out = 1, all_front = 1, all_back = 1;
-    for (int c = 0; c < nc; ++c) {
-        int in = vo_in_fov(t, p, cq[c]);
-        double dn = t->normal_sign * (cq[c][t->normal_axis] - t->center[t->normal_axis]);
-        all_in = all_in && in;
-        all_out = all_out && !in;
-        all_front = all_front && dn >= 0.0;
-        all_back = all_back && dn < 0.0;
+    /* the region of a viewer-centric map: the ball is convex, so corners
+     * inside put the box inside; the box is outside when its nearest point
+     * to the viewer is farther than d_max */
+    int region = 1;
+    if (t->kind == VO_VIEWER) {
+        int all_in = 1;
+        double g2 = 0.0;
+        for (int c = 0; c < nc; ++c)
+            all_in = all_in && in_region(t, cq[c]);
+        for (int k = 0; k < 3; ++k) {
+            double lo = cq[0][k], hi = cq[nc - 1][k], x = t->center[k];
+            double gap = x < lo ? lo - x : (x > hi ? x - hi : 0.0);
+            g2 += gap * gap;
+        }
+        region = all_in ? 1 : (g2 > t->size[0] * t->size[0] ? 0 : -1);
+        if (region == 0)
+            return 0;
     }
-    if (half <= 90.0)
-        return all_in ? 1 : (all_back ? 0 : -1);
-    return all_front ? 1 : (all_out ? 0 : -1);
+    int wedge;
+    double half = p->fov_deg / 2.0;
+    if (half >= 180.0) {
+        wedge = 1;
+    } else {
+        int all_in = 1, all_out = 1, all_front = 1, all_back = 1;
+        for (int c = 0; c < nc; ++c) {
+            int in = in_wedge(t, p, cq[c]);
+            double dn = t->normal_sign * (cq[c][t->normal_axis] - t->center[t->normal_axis]);
+            all_in = all_in && in;
+            all_out = all_out && !in;
+            all_front = all_front && dn >= 0.0;
+            all_back = all_back && dn < 0.0;
+        }
+        if (half <= 90.0)
+            wedge = all_in ? 1 : (all_back ? 0 : -1);
+        else
+            wedge = all_front ? 1 : (all_out ? 0 : -1);
+    }
+    if (wedge == 0)
+        return 0;
+    return (region == 1 && wedge == 1) ? 1 : -1;
 }
 
 /* Classify the block of viewpoints with grid indices lo[a] .. hi[a]
@@ -1101,8 +1189,8 @@ int vo_eval_pruned(int dim, int64_t nbox, const double *lo, const double *hi,
     if (load_boxes(dim, nbox, lo, hi, t, &blo, &bhi))
         return -1;
     vo_cells cells;
-    double mu = p->mu_arcmin * VO_PI / (180.0 * 60.0);
-    if (vo_partition(target_size(t), mu, p->d0, &cells)) {
+    double mu = mu_rad(p);
+    if (partition(target_size(t, p), mu, p->d0, t->kind == VO_VIEWER, &cells)) {
         free(blo);
         free(bhi);
         return -1;

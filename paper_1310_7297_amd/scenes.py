@@ -25,10 +25,12 @@ import numpy as np
 QUANTUM = 1.0 / 256.0
 COORD_LIMIT = float(2 ** 14)
 
-# Target kinds (match the C-ABI enum values).
+# Target kinds (match the C-ABI enum values).  VIEWER: the viewer of a
+# viewer-centric map, size[0] = the radius d_max of the region it covers.
 SEGMENT = 0
 BILLBOARD = 1
 CUBE = 2
+VIEWER = 3
 
 # Modes, methods, bin scales (match the C-ABI enum values).
 FULL = 0
@@ -83,6 +85,8 @@ class Target:
         c = np.asarray(self.center, dtype=np.float64)
         lo = c.copy()
         hi = c.copy()
+        if self.kind == VIEWER:
+            return lo, hi
         if self.kind == CUBE:
             e = self.size[0] / 2.0
             return c - e, c + e

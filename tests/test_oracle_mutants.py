@@ -39,12 +39,12 @@ MUTANTS = [
      "        double V = V0 - k * mu;", "        double V = V0 - (k + 1) * mu;",
      [P + "test_rings_step_the_facing_angle_by_mu"]),
     ("cell colour taken at the ring's inner radius",
-     "    double dp = 0.5 * (c->d[i] + c->d[i + 1]);\n    double gm = 0.5 * (g[j] + g[j + 1]);\n    return",
-     "    double dp = c->d[i];\n    double gm = 0.5 * (g[j] + g[j + 1]);\n    return",
+     "    double dp = 0.5 * (c->d[i] + c->d[i + 1]);\n    double gm = 0.5 * (g[j] + g[j + 1]);\n    if",
+     "    double dp = c->d[i];\n    double gm = 0.5 * (g[j] + g[j + 1]);\n    if",
      [P + "test_cell_colour_is_the_visual_angle_at_the_parameter_midpoint"]),
     ("cell colour taken at the band's upper edge",
-     "    double gm = 0.5 * (g[j] + g[j + 1]);\n    return vis_angle",
-     "    double gm = g[j];\n    return vis_angle",
+     "    double gm = 0.5 * (g[j] + g[j + 1]);\n    if (c->rings_only)",
+     "    double gm = g[j];\n    if (c->rings_only)",
      [P + "test_cell_colour_is_the_visual_angle_at_the_parameter_midpoint"]),
     ("VCM_M takes the highest ring instead of the lowest",
      "    for (int i = 0; i < c->nring && !found; ++i) {",
@@ -75,7 +75,7 @@ MUTANTS = [
      "            for (int c = 0; c < nc && all; ++c)", "            for (int c = 0; c < 1 && all; ++c)",
      ["tests/test_oracle_blocks.py::test_decided_blocks_agree_with_brute_force_everywhere"]),
     ("wide field of view taken as convex",
-     "    return all_front ? 1 : (all_out ? 0 : -1);", "    return all_in ? 1 : (all_out ? 0 : -1);",
+     "            wedge = all_front ? 1 : (all_out ? 0 : -1);", "            wedge = all_in ? 1 : (all_out ? 0 : -1);",
      ["tests/test_oracle_blocks.py::test_block_hand_cases"]),
     ("live faces not checked for the whole block",
      "        uniform = m == n && memcmp(smp, tmp, sizeof(double) * 3 * (size_t)n) == 0;",
@@ -85,6 +85,15 @@ MUTANTS = [
     ("FRACTION-mode block decided with one sample undecided",
      "    if (seen + hidden == n) {", "    if (seen + hidden >= n - 1) {",
      ["tests/test_oracle_blocks.py::test_decided_blocks_agree_with_brute_force_everywhere"]),
+    ("viewer size taken as d_max mu instead of 2 d_max tan(mu / 2)",
+     "        return 2.0 * t->size[0] * tan(mu_rad(p) / 2.0);", "        return t->size[0] * mu_rad(p);",
+     ["tests/test_oracle_viewer.py::test_size_gives_mu_at_dmax"]),
+    ("viewer region open at d_max",
+     "    return r2 <= t->size[0] * t->size[0];", "    return r2 < t->size[0] * t->size[0];",
+     ["tests/test_oracle_viewer.py::test_region_is_the_closed_ball"]),
+    ("viewer cells coloured at the band's middle angle",
+     "    if (c->rings_only)\n        gm = VO_PI / 2.0;\n", "",
+     ["tests/test_oracle_viewer.py::test_viewer_cells_are_rings"]),
     ("error bounds count the bands above the stated angle",
      "                if (g[j + 1] < lim[m])", "                if (g[j + 1] > lim[m])",
      [P + "test_measured_error_within_the_printed_bounds"]),
