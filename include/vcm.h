@@ -104,7 +104,8 @@ vcm_status vcm_index_get_info(const vcm_index *index, vcm_index_info *info);
 typedef enum {
     VCM_SEGMENT = 0,   /* 2-D line target (Sec. III uses it for exposition) */
     VCM_BILLBOARD = 1, /* 3-D vertical rectangle                            */
-    VCM_CUBE = 2       /* 3-D axis-aligned cube                             */
+    VCM_CUBE = 2,      /* 3-D axis-aligned cube                             */
+    VCM_VIEWER = 3     /* 2-D or 3-D: the viewer of a viewer-centric map    */
 } vcm_target_kind;
 
 /* Target T.  Segment: length size[0], lying along the axis orthogonal to
@@ -115,9 +116,19 @@ typedef enum {
  * T only if it sees every live sample (Def. 2.3).  For the cube, a face's
  * samples are live only for viewpoints strictly outside its plane.  The
  * paper's size S in Eq. 1 is the largest of the target's dimensions. */
+/* Viewer (Sec. IV-B): the viewer-centric map of a viewer at `center`
+ * covers the closed ball of radius d_max = size[0] about it (2^-8 lattice);
+ * the size S entering Eq. 1 is the one whose visual angle at d_max is mu,
+ * S = 2 d_max tan(mu / 2), and every point is taken to face the viewer (no
+ * foreshortening).  One sample, the viewer itself (samples_u = samples_v =
+ * 1); a point of the map is seen when the segment to the viewer meets no
+ * obstacle (by the symmetry of visibility).  normal_axis / normal_sign
+ * orient the field of view (the gaze) and the meridian plane of the MBR and
+ * tangent approximations; the pruned methods' cells are the distance rings,
+ * one band each.  Points outside the ball get count 0 and colour 0. */
 typedef struct {
     int32_t kind;
-    int32_t normal_axis;   /* segment, billboard: 0 or 1                    */
+    int32_t normal_axis;   /* segment, billboard, viewer: 0 or 1            */
     int32_t normal_sign;   /* +1 or -1: orientation of the FOV wedge        */
     int32_t samples_u;     /* 1..64                                         */
     int32_t samples_v;     /* 1..64 (segment: 1)                            */
@@ -206,6 +217,11 @@ typedef struct {
                                 |V_approx - V_E| (radians, no visibility
                                 gate) times the area (2-D) or volume (3-D)
                                 of one lattice cell                         */
+    uint64_t blocks;         /* visible-region blocks classified (Sec.
+                                III-C-1), over every level of the tree      */
+    uint64_t blocks_decided; /* of which decided as a whole                  */
+    uint64_t leaves;         /* undecided smallest blocks, traced at their
+                                representative viewpoint                    */
 } vcm_stats;
 
 /* Results: caller-owned buffers of grid.n[0]*n[1]*n[2] entries.

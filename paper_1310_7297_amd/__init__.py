@@ -91,7 +91,9 @@ class vcm_stats(ctypes.Structure):
                 ("t_fallbacks", ctypes.c_uint64), ("records", ctypes.c_uint64),
                 ("narrow_tests", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
                 ("err_signed", ctypes.c_double), ("err_abs", ctypes.c_double),
-                ("bound", ctypes.c_double), ("bound_measured", ctypes.c_double)]
+                ("bound", ctypes.c_double), ("bound_measured", ctypes.c_double),
+                ("blocks", ctypes.c_uint64), ("blocks_decided", ctypes.c_uint64),
+                ("leaves", ctypes.c_uint64)]
 
 
 class vcm_result(ctypes.Structure):

@@ -11,7 +11,8 @@ OUT = os.path.join(HERE, "libvcm.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "index.hip", "brute.hip", "pruned.hip", "error.hip", "batch.hip", "serve.hip", "tune.hip"]
+SOURCES = ["api.hip", "index.hip", "brute.hip", "blocks.hip", "pruned.hip", "error.hip", "batch.hip", "serve.hip",
+           "tune.hip"]
 
 # Packed float32 instructions are disabled for every HIP translation unit.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -72,10 +72,14 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
     const vcm_params &P = q.params;
     const int dim = ix.dim;
     // ---- target
-    if (T.kind != VCM_SEGMENT && T.kind != VCM_BILLBOARD && T.kind != VCM_CUBE)
+    if (T.kind != VCM_SEGMENT && T.kind != VCM_BILLBOARD && T.kind != VCM_CUBE && T.kind != VCM_VIEWER)
         return set_error(VCM_E_INVALID, "unknown target kind");
-    if ((T.kind == VCM_SEGMENT) != (dim == 2))
-        return set_error(VCM_E_INVALID, "segment targets need a 2-D index, others a 3-D index");
+    if (T.kind != VCM_VIEWER && (T.kind == VCM_SEGMENT) != (dim == 2))
+        return set_error(VCM_E_INVALID, "segment targets need a 2-D index, billboards and cubes a 3-D index");
+    if (T.kind == VCM_VIEWER && (T.samples_u != 1 || T.samples_v != 1))
+        return set_error(VCM_E_INVALID, "a viewer has samples_u = samples_v = 1");
+    if (T.kind == VCM_VIEWER && dim == 2 && T.center[2] != 0.0)
+        return set_error(VCM_E_INVALID, "a 2-D viewer has center[2] = 0");
     if (T.samples_u < 1 || T.samples_u > 64 || T.samples_v < 1 || T.samples_v > 64)
         return set_error(VCM_E_INVALID, "samples_u and samples_v must be in [1, 64]");
     if (T.kind == VCM_SEGMENT && T.samples_v != 1)
@@ -94,7 +98,10 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
         if (!dyadic(T.center[k])) return set_error(VCM_E_INVALID, "target centre off the 2^-8 lattice");
     double half[3] = {0, 0, 0};
     double su_len = T.size[0], sv_len = 0;
-    if (T.kind == VCM_CUBE) {
+    if (T.kind == VCM_VIEWER) {
+        su_len = 0;  // a point: one sample at the centre
+        if (!dyadic(T.size[0])) return set_error(VCM_E_INVALID, "a viewer's d_max (size[0]) must be on the 2^-8 lattice");
+    } else if (T.kind == VCM_CUBE) {
         half[0] = half[1] = half[2] = T.size[0] / 2;
         sv_len = T.size[0];
     } else {
@@ -117,7 +124,11 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
         if (!dyadic((2 * i + 1 - T.samples_v) * hv) || !dyadic(T.center[2] + (2 * i + 1 - T.samples_v) * hv) ||
             !dyadic(T.center[1] + (2 * i + 1 - T.samples_v) * hv))
             return set_error(VCM_E_INVALID, "sample lattice off the 2^-8 lattice (size / samples_v)");
-    const double S = T.kind == VCM_BILLBOARD ? std::max(T.size[0], T.size[1]) : T.size[0];
+    const double mu_p = deg2rad(P.mu_arcmin / 60.0);
+    // a viewer's S: the size whose visual angle at d_max is mu (Sec. IV-B)
+    const double S = T.kind == VCM_BILLBOARD ? std::max(T.size[0], T.size[1])
+                     : T.kind == VCM_VIEWER  ? 2.0 * T.size[0] * std::tan(mu_p / 2.0)
+                                             : T.size[0];
     if (target_meets_obstacle(ix, T.center, half))
         return set_error(VCM_E_INVALID, "the target's box meets an obstacle");
     // ---- grid
@@ -180,6 +191,7 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
     t->hu = (float)hu;
     t->hv = (float)hv;
     t->S = (float)S;
+    t->rmax = T.kind == VCM_VIEWER ? (float)T.size[0] : 0.0f;
 
     *g = GridDesc{};
     for (int k = 0; k < 3; ++k) {
@@ -231,28 +243,27 @@ namespace {
 constexpr size_t kWsAlign = 256;
 size_t ws_align(size_t x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
 
-int64_t block_count(const GridDesc &g, int theta, int32_t gn[3]) {
-    int64_t nrep = 1;
-    for (int k = 0; k < 3; ++k) {
-        gn[k] = (g.n[k] + theta - 1) / theta;
-        nrep *= gn[k];
-    }
-    return nrep;
-}
-
 }  // namespace
 
-// Workspace layout: the work-item range counters, then (pruned methods) one
-// gate word per block and, with statistics, the colouring's partial sums.
-WsLayout query_workspace(const GridDesc &g, int method, int theta, bool stats) {
+// Workspace layout: the work-item range counters of the ray kernel; for the
+// pruned methods, one gate word per viewpoint, the block lists of the
+// visible-region tree, their counters and, with sums, the colouring's
+// partial sums.
+WsLayout query_workspace(const GridDesc &g, int dim, int method, int theta, bool sums) {
     WsLayout w;
     w.counter = 0;
     size_t off = ws_align(kCounterBytes);
     if (method != VCM_BRUTE && g.count > 0) {
-        int32_t gn[3];
+        w.plan = block_plan(g, dim, theta);
         w.gate = off;
-        off += ws_align(sizeof(uint32_t) * static_cast<size_t>(block_count(g, theta, gn)));
-        if (stats) {
+        off += ws_align(sizeof(uint32_t) * static_cast<size_t>(g.count));
+        for (int l = 1; l <= w.plan.levels; ++l) {
+            w.lists[l] = off;
+            off += ws_align(sizeof(uint32_t) * static_cast<size_t>(w.plan.count[std::min(l, w.plan.levels - 1)]));
+        }
+        w.ctr = off;
+        off += ws_align(sizeof(unsigned) * 2 * (w.plan.levels + 1));
+        if (sums) {
             w.sums = off;
             w.n_sums = pruned_sum_blocks(g);
             off += ws_align(sizeof(double) * kPrunedSums * static_cast<size_t>(w.n_sums));
@@ -264,18 +275,26 @@ WsLayout query_workspace(const GridDesc &g, int method, int theta, bool stats) {
 
 vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
                      int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats,
-                     char *ws) {
+                     char *ws, bool sums) {
     const Tuning tune{};
-    const WsLayout w = query_workspace(g, method, theta, stats != nullptr);
+    const WsLayout w = query_workspace(g, ix.dim, method, theta, sums);
     unsigned *counter = reinterpret_cast<unsigned *>(ws + w.counter);
     if (method == VCM_BRUTE) return launch_brute(ix, t, g, p, r, s, stats, nullptr, 1, tune, counter);
-    // pruned: gate at the block representatives, then the cell colours
-    int32_t gn[3];
-    block_count(g, theta, gn);
+    if (g.count <= 0) return VCM_OK;
+    if (g.count >= (int64_t(1) << 32))
+        return set_error(VCM_E_INVALID, "pruned methods take grids of fewer than 2^32 viewpoints");
+    // pruned: the visible-region blocks, the representatives of the undecided
+    // smallest ones, then the cell colours of every viewpoint
     uint32_t *gate = reinterpret_cast<uint32_t *>(ws + w.gate);
-    vcm_status st = launch_brute(ix, t, g, p, r, s, stats, gate, theta, tune, counter);
+    uint32_t *lists[kMaxBlockLevels + 1] = {};
+    for (int l = 1; l <= w.plan.levels; ++l) lists[l] = reinterpret_cast<uint32_t *>(ws + w.lists[l]);
+    unsigned *ctr = reinterpret_cast<unsigned *>(ws + w.ctr);
+    vcm_status st = launch_blocks(ix, t, g, p, w.plan, gate, lists, ctr, s, stats);
+    const int lv = block_classified_levels(w.plan);
     if (st == VCM_OK)
-        st = launch_pruned(ix, t, g, p, method, theta, gate, gn, r, s, stats ? &stats->t_fallbacks : nullptr,
+        st = launch_leaves(ix, t, g, p, w.plan, gate, lists[lv], ctr + lv, ctr + 2 * w.plan.levels + 1, s, stats);
+    if (st == VCM_OK)
+        st = launch_pruned(ix, t, g, p, method, gate, r, s, stats ? &stats->t_fallbacks : nullptr,
                            w.n_sums ? reinterpret_cast<double *>(ws + w.sums) : nullptr);
     return st;
 }
@@ -410,7 +429,7 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     DeviceGuard guard(ix.device);
     hipStream_t s = (hipStream_t)stream;
     const int method = query->params.method, theta = query->params.theta_blocks;
-    const WsLayout w = query_workspace(g, method, theta, stats != nullptr);
+    const WsLayout w = query_workspace(g, ix.dim, method, theta, stats != nullptr);
     const size_t n = static_cast<size_t>(std::max<int64_t>(g.count, 0));
 
     // Host result buffers: the maps are computed into device buffers of the
@@ -440,7 +459,7 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
         TRY_HIP(hipMemsetAsync(d_stats, 0, sizeof(DevStats), s));
         TRY_HIP(hipEventRecord(e0, s));
     }
-    st = run_query(ix, t, g, p, method, theta, dev, s, d_stats, ws);
+    st = run_query(ix, t, g, p, method, theta, dev, s, d_stats, ws, stats != nullptr);
     if (stats && st == VCM_OK) TRY_HIP(hipEventRecord(e1, s));
     std::vector<double> sums(static_cast<size_t>(w.n_sums) * kPrunedSums);
     DevStats h{};
@@ -480,6 +499,9 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query, const vcm
     stats->records = h.records;
     stats->narrow_tests = h.narrow_tests;
     stats->kernel_ms = ms;
+    stats->blocks = h.blocks;
+    stats->blocks_decided = h.blocks_decided;
+    stats->leaves = h.leaves;
     if (method != VCM_BRUTE) {
         // Sec. V-A error against the reference map, and the Sec. IV-A
         // comparison: the summed |V_approx - V_E| times the size each
@@ -517,7 +539,7 @@ vcm_status vcm_compute_noalloc(const vcm_index *index, const vcm_query *query,
     vcm_status st = prepare_query(ix, *query, &t, &g, &p);
     if (st != VCM_OK) return st;
     const int method = query->params.method, theta = query->params.theta_blocks;
-    const size_t need = query_workspace(g, method, theta, false).bytes;
+    const size_t need = query_workspace(g, ix.dim, method, theta, false).bytes;
     if (need > kScratchBytes)
         return set_error(VCM_E_INVALID, "vcm_compute_noalloc: the query needs " + std::to_string(need) +
                                             " bytes of scratch memory, more than the " +
@@ -526,7 +548,7 @@ vcm_status vcm_compute_noalloc(const vcm_index *index, const vcm_query *query,
     char *ws = nullptr;
     st = scratch_address(ix.device, &ws);
     if (st != VCM_OK) return st;
-    return run_query(ix, t, g, p, method, theta, *result, (hipStream_t)stream, nullptr, ws);
+    return run_query(ix, t, g, p, method, theta, *result, (hipStream_t)stream, nullptr, ws, false);
 }
 
 vcm_status vcm_map_error(const float *c_exact, const float *c_approx, int64_t n, int device,
@@ -542,8 +564,10 @@ vcm_status vcm_error_bounds(const vcm_query *query, int32_t dim, double out[2]) 
     clear_error();
     if (!query || !out || (dim != 2 && dim != 3)) return set_error(VCM_E_INVALID, "invalid arguments");
     const vcm_target &T = query->target;
-    const double S = T.kind == VCM_BILLBOARD ? std::max(T.size[0], T.size[1]) : T.size[0];
     const double mu = query->params.mu_arcmin / 60.0 * M_PI / 180.0;
+    const double S = T.kind == VCM_BILLBOARD ? std::max(T.size[0], T.size[1])
+                     : T.kind == VCM_VIEWER  ? 2.0 * T.size[0] * std::tan(mu / 2.0)
+                                             : T.size[0];
     const double d0 = query->params.near_d0;
     if (!(S > 0) || !(mu > 0) || !(d0 > 0) || !(2.0 * std::atan(S / (2.0 * d0)) > mu))
         return set_error(VCM_E_INVALID, "target size, mu and near point must be positive, V0 > mu");

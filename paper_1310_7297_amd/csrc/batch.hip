@@ -4,8 +4,8 @@
 // kernel they need (precision and mode); each group is one persistent launch
 // over the work items of all its queries, so small and large maps share the
 // machine instead of running one under-filled launch after another.  Pruned
-// queries take part with their block representatives (gate mode) and are
-// coloured by one pruned launch each afterwards.
+// queries run their visible-region tree and colouring afterwards, one query
+// after another (run_query).
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -109,12 +109,10 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Work items of one query at a given chunk (gate mode: the block grid).
+// Work items of one brute-force query at a given chunk.
 uint64_t query_items(const PlanQuery &q, int chunk) {
-    int32_t n[3];
-    for (int k = 0; k < 3; ++k) n[k] = q.method == VCM_BRUTE ? q.g.n[k] : q.gn[k];
-    const uint64_t cpr = (static_cast<uint64_t>(n[0]) + chunk - 1) / chunk;
-    return cpr * static_cast<uint64_t>(n[1]) * static_cast<uint64_t>(n[2]);
+    const uint64_t cpr = (static_cast<uint64_t>(q.g.n[0]) + chunk - 1) / chunk;
+    return cpr * static_cast<uint64_t>(q.g.n[1]) * static_cast<uint64_t>(q.g.n[2]);
 }
 
 }  // namespace
@@ -136,11 +134,6 @@ vcm_status BatchPlan::prepare(const Index &index, const vcm_query *qs, int nq, c
         pq.ns = slots_for(pq.t);
         if (pq.ns < 1 || pq.ns > kMaxSlots)
             return set_error(VCM_E_INVALID, "query " + std::to_string(i) + ": too many target samples");
-        pq.nrep = 1;
-        for (int k = 0; k < 3; ++k) {
-            pq.gn[k] = (pq.g.n[k] + pq.theta - 1) / pq.theta;
-            pq.nrep *= pq.gn[k];
-        }
         if (pq.g.count >= (int64_t(1) << 31))
             return set_error(VCM_E_INVALID, "query " + std::to_string(i) + ": grid too large for a batch");
         viewpoints += static_cast<uint64_t>(pq.g.count);
@@ -155,7 +148,7 @@ void BatchPlan::layout() {
     const uint64_t kMaxItems = uint64_t(1) << 31;
     for (size_t i = 0; i < q.size(); ++i) {
         const PlanQuery &pq = q[i];
-        if (pq.g.count <= 0) continue;
+        if (pq.g.count <= 0 || pq.method != VCM_BRUTE) continue;
         const uint64_t wi = query_items(pq, chunk_for(tune, pq.p.mode));
         const uint64_t it = (wi + 3) / 4;  // groups of four work items (one workgroup claim)
         PlanGroup *g = nullptr;
@@ -183,8 +176,9 @@ void BatchPlan::layout() {
     }
     image_bytes = off;
     for (auto &pq : q) {
-        pq.gate_off = off;
-        if (pq.method != VCM_BRUTE && pq.g.count > 0) off = align_up(off + sizeof(uint32_t) * pq.nrep);
+        pq.ws_off = off;
+        if (pq.method != VCM_BRUTE && pq.g.count > 0)
+            off = align_up(off + query_workspace(pq.g, ix->dim, pq.method, pq.theta, false).bytes);
     }
     bytes = std::max<size_t>(off, kAlign);
 }
@@ -197,10 +191,8 @@ void BatchPlan::image(std::vector<char> &img) const {
         uint32_t acc = 0;
         for (size_t m = 0; m < g.members.size(); ++m) {
             const PlanQuery &pq = q[g.members[m]];
-            uint32_t *gate = pq.method == VCM_BRUTE ? nullptr
-                                                    : reinterpret_cast<uint32_t *>(d_base + pq.gate_off);
             const int chunk = chunk_for(tune, pq.p.mode);
-            recs[m] = make_brute_args(*ix, pq.t, pq.g, pq.p, pq.r, gate, pq.theta, chunk);
+            recs[m] = make_brute_args(*ix, pq.t, pq.g, pq.p, pq.r, nullptr, 1, chunk);
             acc += static_cast<uint32_t>((query_items(pq, chunk) + 3) / 4);
             ends[m] = acc;
         }
@@ -222,11 +214,11 @@ vcm_status BatchPlan::enqueue(hipStream_t s, DevStats *stats) const {
                                            static_cast<int>(std::max<int64_t>(blocks, 1)), s);
         if (st != VCM_OK) return st;
     }
+    // pruned queries: their own visible-region tree and colouring, in order
     for (const auto &pq : q) {
         if (pq.method == VCM_BRUTE || pq.g.count <= 0) continue;
-        vcm_status st = launch_pruned(*ix, pq.t, pq.g, pq.p, pq.method, pq.theta,
-                                      reinterpret_cast<const uint32_t *>(d_base + pq.gate_off), pq.gn,
-                                      pq.r, s, stats ? &stats->t_fallbacks : nullptr, nullptr);
+        vcm_status st = run_query(*ix, pq.t, pq.g, pq.p, pq.method, pq.theta, pq.r, s, stats, d_base + pq.ws_off,
+                                  false);
         if (st != VCM_OK) return st;
     }
     return VCM_OK;
@@ -356,6 +348,7 @@ vcm_status autotune(vcm_batch *b, const vcm_query *qs, const vcm_result *rs, int
 }
 
 vcm_status fill_stats(const DevStats &h, uint64_t viewpoints, float ms, vcm_stats *stats) {
+    *stats = vcm_stats{};
     stats->viewpoints = viewpoints;
     stats->rays = h.rays;
     stats->box_tests = h.box_tests;
@@ -368,6 +361,9 @@ vcm_status fill_stats(const DevStats &h, uint64_t viewpoints, float ms, vcm_stat
     stats->records = h.records;
     stats->narrow_tests = h.narrow_tests;
     stats->kernel_ms = ms;
+    stats->blocks = h.blocks;
+    stats->blocks_decided = h.blocks_decided;
+    stats->leaves = h.leaves;
     return VCM_OK;
 }
 

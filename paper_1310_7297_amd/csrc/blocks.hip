@@ -1,0 +1,511 @@
+// Visible-region blocks (Sec. III-C-1) for the pruned constructions.
+//
+// The paper indexes the visible region with a quad-tree (octree) whose
+// blocks are split while they are partly visible, down to a minimum size.
+// Here the tree is built level by level over the viewpoint lattice, one
+// wavefront per block, its lanes holding the target's live samples (64 per
+// slot), so that a block is classified against every obstacle near it at
+// once:
+//   * the live samples and the field of view must be the same over the whole
+//     block (checked at its corners: each live-face condition is a
+//     half-space, and the wedge rules are exact for convex sets);
+//   * a sample is seen from all of the block when no obstacle meets the
+//     convex hull of the block and the sample; it is hidden from all of it
+//     when one obstacle meets the segments from every corner of the block to
+//     the sample (the points whose segment to a sample meets an obstacle form
+//     a convex set); both tests are exact in float64 on the 2^-8 lattice;
+//   * FULL mode: one hidden sample decides the block (count 0), all seen
+//     decide it (count N); FRACTION mode: every sample seen or hidden decides
+//     it (count = seen);
+//   * a decided block writes the gate (count | N << 10 | fov << 20) of every
+//     one of its viewpoints; an undecided one is split into its octants, or,
+//     at the smallest size, listed for the ray kernel, which traces its
+//     representative viewpoint (k_leaves in brute.hip).
+// The candidate obstacles are those of the columns crossed by the convex hull
+// of the block and the target's box, walked slab by slab along the major
+// horizontal axis as for a single viewpoint.
+#include <algorithm>
+#include <cmath>
+
+#include "trace_common.h"
+
+namespace vcm {
+namespace {
+
+// Exact: does the closed box [a, c] meet the convex hull of the box [L, H]
+// and the point s?  The hull is the union over lambda in [0, 1] of the boxes
+// [s + lambda (L - s), s + lambda (H - s)]; per axis, two linear constraints
+// lambda x <= y bound lambda by fractions, compared by cross-multiplication.
+// Differences of lattice coordinates are exact in float32, their products in
+// float64.
+template <int DIM>
+__device__ inline bool hull_meets(const float *L, const float *H, const float *s, const float *a,
+                                  const float *c) {
+    double ln = 0.0, ld = 1.0, un = 1.0, ud = 1.0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const double x = side ? double(s[k] - H[k]) : double(L[k] - s[k]);
+            const double y = side ? double(s[k] - a[k]) : double(c[k] - s[k]);
+            if (x > 0.0) {
+                if (y * ud < un * x) {
+                    un = y;
+                    ud = x;
+                }
+            } else if (x < 0.0) {
+                if (-y * ld > ln * -x) {
+                    ln = -y;
+                    ld = -x;
+                }
+            } else {
+                ok = ok && y >= 0.0;
+            }
+        }
+    return ok && ln * ud <= un * ld;
+}
+
+struct BlockLevel {
+    DevIndex idx;
+    TargetDesc tgt;
+    GridDesc grid;
+    ParamDesc prm;
+    uint32_t *gate;            // per viewpoint: count | N << 10 | fov << 20
+    const uint32_t *in_list;   // blocks of this level (index in its block grid); null: all
+    const uint32_t *in_count;  // entries of in_list
+    uint32_t n_all;            // blocks of this level when in_list is null
+    uint32_t *out_list;        // octants of undecided blocks, or (last level) the blocks
+    uint32_t *out_count;
+    unsigned *claim;           // work counter of this launch
+    DevStats *stats;
+    int32_t side;              // viewpoints per block edge
+    int32_t nb[3];             // blocks per axis at this level
+    int32_t nbc[3];            // blocks per axis one level down (side / 2)
+    int32_t last;              // smallest blocks: undecided ones are listed unsplit
+};
+
+// Position of viewpoint index i along axis k (exact).
+__device__ inline float vp_pos(const GridDesc &g, int k, int i) {
+    return g.o[k] + static_cast<float>(2 * i + 1) * g.h2[k];
+}
+
+// Candidate obstacles of a block: the records of the columns crossed by the
+// convex hull of the box C = [L, H] and the target's box, slab by slab along
+// axis AX from the target end.  `visit(lo, hi)` is called with each
+// candidate's corners and returns true to stop the walk.  Float32 with the
+// same margins as the viewpoint corridor: the walk never drops a column or
+// record the hull reaches (records are inserted with a 2^-6 m margin).
+template <int DIM, int AX, class Visit>
+__device__ inline void block_walk(const BlockLevel &B, cptr_i32 col_start, cptr_rec recs, const float (&L)[3],
+                                  const float (&H)[3], Visit &&visit) {
+    const TargetDesc &T = B.tgt;
+    const DevIndex &X = B.idx;
+    const int lane = threadIdx.x & 63;
+    constexpr int BX = 1 - AX;
+    const float F0[3] = {T.c[0] - T.half[0], T.c[1] - T.half[1], T.c[2] - T.half[2]};
+    const float F1[3] = {T.c[0] + T.half[0], T.c[1] + T.half[1], T.c[2] + T.half[2]};
+    const int na = AX == 0 ? X.nx : X.ny, nb = AX == 0 ? X.ny : X.nx;
+    // the hull is the union over l in [0, 1] of the boxes
+    // [L + l (F0 - L), H + l (F1 - H)]
+    const float ua0 = F0[AX] - L[AX], ua1 = F1[AX] - H[AX];
+    const float iua0 = ua0 != 0.0f ? __builtin_amdgcn_rcpf(ua0) : 0.0f;
+    const float iua1 = ua1 != 0.0f ? __builtin_amdgcn_rcpf(ua1) : 0.0f;
+    const float vb0 = F0[BX] - L[BX], vb1 = F1[BX] - H[BX];
+    const float wz0 = F0[2] - L[2], wz1 = F1[2] - H[2];
+    const float amin = fminf(L[AX], F0[AX]), amax = fmaxf(H[AX], F1[AX]);
+    if (!(amax >= 0.0f && amin < na * X.cs)) return;
+    const int ia_lo = max(0, min(na - 1, static_cast<int>(floorf(amin * X.inv_cs))));
+    const int ia_hi = max(0, min(na - 1, static_cast<int>(floorf(amax * X.inv_cs))));
+    const float ca = 0.5f * (L[AX] + H[AX]);
+    const int step = (ca <= T.c[AX]) ? -1 : 1;
+    for (int s = 0; s <= ia_hi - ia_lo; ++s) {
+        const int ia = step < 0 ? ia_hi - s : ia_lo + s;
+        const float A0 = ia * X.cs, A1 = A0 + X.cs;
+        float l0 = 0.0f, l1 = 1.0f;
+        bool ok = true;
+        const float r1 = A1 - L[AX], r2 = A0 - H[AX];
+        if (ua0 > 0.0f) l1 = fminf(l1, r1 * iua0);
+        else if (ua0 < 0.0f) l0 = fmaxf(l0, r1 * iua0);
+        else ok = ok && r1 >= 0.0f;
+        if (ua1 > 0.0f) l0 = fmaxf(l0, r2 * iua1);
+        else if (ua1 < 0.0f) l1 = fminf(l1, r2 * iua1);
+        else ok = ok && r2 <= 0.0f;
+        l0 = fmaxf(0.0f, l0 - kLambdaMargin);
+        l1 = fminf(1.0f, l1 + kLambdaMargin);
+        if (!ok || l0 > l1) continue;
+        const float bl = fminf(L[BX] + l0 * vb0, L[BX] + l1 * vb0) - kWalkMargin;
+        const float bh = fmaxf(H[BX] + l0 * vb1, H[BX] + l1 * vb1) + kWalkMargin;
+        const float zf = fminf(L[2] + l0 * wz0, L[2] + l1 * wz0) - kWalkMargin;
+        const float zc = fmaxf(H[2] + l0 * wz1, H[2] + l1 * wz1) + kWalkMargin;
+        if (!(bh >= 0.0f && bl < nb * X.cs)) continue;
+        const int ib0 = max(0, min(nb - 1, static_cast<int>(floorf(bl * X.inv_cs))));
+        const int ib1 = max(0, min(nb - 1, static_cast<int>(floorf(bh * X.inv_cs))));
+        for (int ib = ib0; ib <= ib1; ++ib) {
+            const int col = AX == 0 ? ia + X.nx * ib : ib + X.nx * ia;
+            const int cb = col_start[col], ce = col_start[col + 1] - 1;
+            for (int base = cb;; base += 64) {
+                const BoxRec R = recs[min(base + lane, ce)];
+                // lists are sorted by decreasing top and end with a sentinel
+                // whose top is -inf: the scan ends below the hull's floor
+                const bool above = R.hi[2] >= zf;
+                const bool cand = above && R.id >= 0 && R.hi[BX] >= bl && R.lo[BX] <= bh &&
+                                  (DIM == 2 || R.lo[2] <= zc);
+                unsigned long long cm = __ballot(cand);
+                const unsigned long long below = __ballot(!above);
+                while (cm) {
+                    const int r = __builtin_ctzll(cm);
+                    cm &= cm - 1;
+                    float lo[3], hi[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        lo[k] = readlane_f(R.lo[k], r);
+                        hi[k] = readlane_f(R.hi[k], r);
+                    }
+                    if (visit(lo, hi)) return;
+                }
+                if (below) break;
+            }
+        }
+    }
+}
+
+// Field of view over the block (corners q[c]): 1 all inside, 0 all outside,
+// -1 undecided (see the header comment).
+template <int DIM>
+__device__ inline int fov_class(const TargetDesc &T, const ParamDesc &P, const float (&L)[3], const float (&H)[3]) {
+    // a viewer's ball is convex: corners inside put the block inside; the
+    // block is outside when its nearest point to the viewer is beyond rmax
+    int region = 1;
+    if (T.kind == VCM_VIEWER) {
+        bool all_in = true;
+        double g2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < (1 << DIM); ++c) {
+            float q[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) q[k] = ((c >> k) & 1) ? H[k] : L[k];
+            all_in = all_in && in_region<DIM>(T, q);
+        }
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const double x = T.c[k];
+            const double gap = x < L[k] ? double(L[k]) - x : (x > H[k] ? x - double(H[k]) : 0.0);
+            g2 += gap * gap;
+        }
+        region = all_in ? 1 : (g2 > double(T.rmax) * double(T.rmax) ? 0 : -1);
+        if (region == 0) return 0;
+    }
+    if (P.fov_kind == kFovAll) return region;
+    bool all_in = true, all_out = true, all_front = true, all_back = true;
+#pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c) {
+        float q[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[k] = ((c >> k) & 1) ? H[k] : L[k];
+        const bool in = in_wedge<DIM>(T, P, q);
+        const double dn = T.nsign * (double(q[T.nax]) - double(T.c[T.nax]));
+        all_in = all_in && in;
+        all_out = all_out && !in;
+        all_front = all_front && dn >= 0.0;
+        all_back = all_back && dn < 0.0;
+    }
+    // a wedge no wider than a half-space is convex; a wider one has a convex
+    // complement and contains the half-space in front of the target
+    const int wedge = P.fov_kind != kFovWide ? (all_in ? 1 : (all_back ? 0 : -1))
+                                             : (all_front ? 1 : (all_out ? 0 : -1));
+    if (wedge == 0) return 0;
+    return (region == 1 && wedge == 1) ? 1 : -1;
+}
+
+// Live faces over the block: packed face codes (as the ray kernel packs them)
+// and their number; false if a face is live for part of the block only.
+__device__ inline bool live_faces(const TargetDesc &T, const float (&L)[3], const float (&H)[3], unsigned &faces,
+                                  int &nf) {
+    faces = 0;
+    nf = 0;
+    if (T.kind != VCM_CUBE) {
+        nf = 1;
+        return true;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float up = T.c[k] + T.half[k], dn = T.c[k] - T.half[k];
+        // the +k face is live where q_k > up, the -k face where q_k < dn
+        const bool up_lo = L[k] > up, up_hi = H[k] > up;
+        const bool dn_lo = L[k] < dn, dn_hi = H[k] < dn;
+        if (up_lo != up_hi || dn_lo != dn_hi) return false;
+        if (up_lo) faces |= static_cast<unsigned>(2 * k + 1) << (4 * nf++);
+        if (dn_lo) faces |= static_cast<unsigned>(2 * k) << (4 * nf++);
+    }
+    return true;
+}
+
+// Block-hierarchy statistics of one wavefront.
+struct BlockStats {
+    unsigned long long blocks = 0, decided = 0, hull_tests = 0, cols = 0;
+};
+
+// One level of the tree.
+template <int DIM, int NS, int MODE>
+__global__ __launch_bounds__(256) void k_blocks(BlockLevel B, const int32_t *col_start_g, const BoxRec *recs_g) {
+    const cptr_i32 col_start = (cptr_i32)col_start_g;
+    const cptr_rec recs = (cptr_rec)recs_g;
+    __shared__ float4 s_tab[kTableMax];
+    build_sample_table<DIM>(B.tgt, s_tab);
+    const TargetDesc &T = B.tgt;
+    const GridDesc &G = B.grid;
+    const int lane = threadIdx.x & 63;
+    const uint32_t n_in = B.in_list ? *B.in_count : B.n_all;
+    BlockStats st;
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(B.claim, 1u);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
+        if (item >= n_in) break;
+        const uint32_t b = B.in_list ? B.in_list[item] : item;
+        int bi[3] = {static_cast<int>(b % static_cast<uint32_t>(B.nb[0])),
+                     static_cast<int>((b / static_cast<uint32_t>(B.nb[0])) % static_cast<uint32_t>(B.nb[1])),
+                     static_cast<int>(b / (static_cast<uint32_t>(B.nb[0]) * static_cast<uint32_t>(B.nb[1])))};
+        int lo[3], hi[3];
+        float L[3], H[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = bi[k] * B.side;
+            hi[k] = min(lo[k] + B.side, G.n[k]) - 1;
+            if (k >= DIM) lo[k] = hi[k] = 0;
+            L[k] = k < DIM ? vp_pos(G, k, lo[k]) : 0.0f;
+            H[k] = k < DIM ? vp_pos(G, k, hi[k]) : 0.0f;
+        }
+        ++st.blocks;
+        // ---- classification
+        unsigned faces = 0;
+        int nf = 0;
+        const bool uni = live_faces(T, L, H, faces, nf);
+        const int fc = fov_class<DIM>(T, B.prm, L, H);
+        const int N = nf * T.per_facet;
+        bool decided = false;
+        int count = 0;
+        if (uni && fc >= 0) {
+            if (fc == 0 || N == 0) {
+                decided = true;
+            } else {
+                // lanes hold the live samples
+                float sp[NS][3];
+                unsigned long long live[NS], seen[NS], hidden[NS];
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    const int si = j * 64 + lane;
+                    live[j] = __ballot(si < N);
+                    sample_pos<DIM, kTabBlock>(T, faces, si < N ? si : 0, sp[j], s_tab);
+                    seen[j] = live[j];
+                    hidden[j] = 0;
+                }
+                bool stop = false;
+                auto visit = [&](const float (&a)[3], const float (&c)[3]) -> bool {
+                    bool all_hidden = true;
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) {
+                        const unsigned long long todo = live[j] & ~hidden[j];
+                        if (!todo) continue;
+                        bool meet = false, hid = false;
+                        if ((todo >> lane) & 1) {
+                            meet = hull_meets<DIM>(L, H, sp[j], a, c);
+                            if (meet) {
+                                // hidden from the whole block if the box cuts
+                                // the segment from every corner to the sample
+                                hid = true;
+#pragma unroll 1
+                                for (int cn = 0; cn < (1 << DIM) && hid; ++cn) {
+                                    float d[3], lq[3], hq[3];
+#pragma unroll
+                                    for (int k = 0; k < 3; ++k) {
+                                        const float qk = ((cn >> k) & 1) ? H[k] : L[k];
+                                        d[k] = sp[j][k] - qk;
+                                        lq[k] = a[k] - qk;
+                                        hq[k] = c[k] - qk;
+                                    }
+                                    hid = hid && exact_contact<DIM>(d, lq, hq);
+                                }
+                            }
+                        }
+                        st.hull_tests += __popcll(todo);
+                        seen[j] &= ~__ballot(meet);
+                        hidden[j] |= __ballot(hid);
+                        if (MODE == VCM_FULL && hidden[j]) {
+                            stop = true;
+                            return true;
+                        }
+                        all_hidden = all_hidden && hidden[j] == live[j];
+                    }
+                    // FRACTION mode: nothing left to learn once all are hidden
+                    if (MODE == VCM_FRACTION && all_hidden) {
+                        stop = true;
+                        return true;
+                    }
+                    return false;
+                };
+                const float dx = fabsf(T.c[0] - 0.5f * (L[0] + H[0])), dy = fabsf(T.c[1] - 0.5f * (L[1] + H[1]));
+                if (dx >= dy) block_walk<DIM, 0>(B, col_start, recs, L, H, visit);
+                else block_walk<DIM, 1>(B, col_start, recs, L, H, visit);
+                (void)stop;
+                int n_seen = 0, n_hidden = 0;
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    n_seen += __popcll(seen[j]);
+                    n_hidden += __popcll(hidden[j]);
+                }
+                if (MODE == VCM_FULL) {
+                    if (n_hidden > 0) {
+                        decided = true;
+                        count = 0;
+                    } else if (n_seen == N) {
+                        decided = true;
+                        count = N;
+                    }
+                } else if (n_seen + n_hidden == N) {
+                    decided = true;
+                    count = n_seen;
+                }
+            }
+        }
+        if (decided) {
+            // the gate of every viewpoint of the block
+            ++st.decided;
+            const uint32_t word = static_cast<uint32_t>(count) | (static_cast<uint32_t>(N) << 10) |
+                                  (fc > 0 ? (1u << 20) : 0u);
+            const int e0 = hi[0] - lo[0] + 1, e1 = hi[1] - lo[1] + 1, e2 = hi[2] - lo[2] + 1;
+            const int tot = e0 * e1 * e2;
+            for (int t = lane; t < tot; t += 64) {
+                const int i = lo[0] + t % e0, j = lo[1] + (t / e0) % e1, k = lo[2] + t / (e0 * e1);
+                B.gate[i + static_cast<int64_t>(G.n[0]) * (j + static_cast<int64_t>(G.n[1]) * k)] = word;
+            }
+        } else if (B.last) {
+            if (lane == 0) B.out_list[atomicAdd(B.out_count, 1u)] = b;
+        } else {
+            // octants that hold viewpoints, one level down
+            const int half = B.side / 2;
+            int nch = 0;
+            uint32_t mine = 0;
+            for (int o = 0; o < 8; ++o) {
+                int c[3];
+                bool in = true;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    c[k] = 2 * bi[k] + ((o >> k) & 1);
+                    in = in && (k < DIM ? c[k] * half < G.n[k] : c[k] == 0);
+                }
+                if (!in) continue;
+                const uint32_t id = static_cast<uint32_t>(c[0]) +
+                                    static_cast<uint32_t>(B.nbc[0]) *
+                                        (static_cast<uint32_t>(c[1]) + static_cast<uint32_t>(B.nbc[1]) * c[2]);
+                if (lane == nch) mine = id;
+                ++nch;
+            }
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(B.out_count, static_cast<uint32_t>(nch));
+            base = __shfl(base, 0);
+            if (lane < nch) B.out_list[base + lane] = mine;
+        }
+    }
+    if (B.stats && lane == 0) {
+        atomicAdd(&B.stats->blocks, st.blocks);
+        atomicAdd(&B.stats->blocks_decided, st.decided);
+        atomicAdd(&B.stats->hull_tests, st.hull_tests);
+    }
+}
+
+__global__ void k_zero_words(unsigned *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+template <int DIM, int MODE, class F>
+void dispatch_blocks(int ns, F &&f) {
+    if (ns <= 1) f(std::integral_constant<int, 1>{});
+    else if (ns == 2) f(std::integral_constant<int, 2>{});
+    else if (ns == 3) f(std::integral_constant<int, 3>{});
+    else f(std::integral_constant<int, 6>{});
+}
+
+}  // namespace
+
+int block_classified_levels(const BlockPlan &bp) { return bp.leaf == 1 ? bp.levels - 1 : bp.levels; }
+
+int block_leaf_side(int theta) {
+    int s = 1;
+    while (2 * s <= theta) s *= 2;
+    return s;
+}
+
+BlockPlan block_plan(const GridDesc &g, int dim, int theta) {
+    BlockPlan bp;
+    bp.leaf = block_leaf_side(theta);
+    bp.root = std::max(bp.leaf, kRootBlockSide);
+    bp.levels = 0;
+    for (int s = bp.root; s >= bp.leaf; s /= 2) {
+        int64_t n = 1;
+        for (int k = 0; k < 3; ++k) n *= k < dim ? (g.n[k] + s - 1) / s : 1;
+        bp.side[bp.levels] = s;
+        bp.count[bp.levels] = n;
+        ++bp.levels;
+    }
+    return bp;
+}
+
+vcm_status launch_blocks(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
+                         const BlockPlan &bp, uint32_t *gate, uint32_t *const *lists, unsigned *ctr,
+                         hipStream_t s, DevStats *stats) {
+    // ctr: [0, levels] entry counts of lists[1..levels] (the last is the list
+    // of undecided smallest blocks), then one work counter per launch
+    const int nctr = 2 * (bp.levels + 1);
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, ctr, nctr);
+    const int cus = device_cus(ix.device);
+    const int ns = slots_for(t);
+    // single viewpoints are not classified: the ray kernel traces them (a
+    // one-viewpoint block is always decidable, but tracing is cheaper)
+    const int classified = block_classified_levels(bp);
+    for (int l = 0; l < classified; ++l) {
+        BlockLevel B{};
+        B.idx = ix.dev;
+        B.tgt = t;
+        B.grid = g;
+        B.prm = p;
+        B.gate = gate;
+        B.in_list = l == 0 ? nullptr : lists[l];
+        B.in_count = l == 0 ? nullptr : ctr + l;
+        B.n_all = static_cast<uint32_t>(bp.count[0]);
+        B.out_list = lists[l + 1];
+        B.out_count = ctr + l + 1;
+        B.claim = ctr + bp.levels + 1 + l;
+        B.stats = stats;
+        B.side = bp.side[l];
+        B.last = l == bp.levels - 1;
+        const int half = std::max(1, bp.side[l] / 2);
+        for (int k = 0; k < 3; ++k) {
+            B.nb[k] = k < ix.dim ? (g.n[k] + B.side - 1) / B.side : 1;
+            B.nbc[k] = k < ix.dim ? (g.n[k] + half - 1) / half : 1;
+        }
+        const int64_t want = l == 0 ? (bp.count[0] + 3) / 4 : int64_t(cus) * 8;
+        const dim3 grid(static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(cus) * 8))));
+        auto go = [&](auto nsv) {
+            constexpr int NS = decltype(nsv)::value;
+            if (ix.dim == 2) {
+                if (p.mode == VCM_FULL)
+                    hipLaunchKernelGGL((k_blocks<2, NS, VCM_FULL>), grid, dim3(256), 0, s, B, ix.dev.col_start, ix.dev.recs);
+                else
+                    hipLaunchKernelGGL((k_blocks<2, NS, VCM_FRACTION>), grid, dim3(256), 0, s, B, ix.dev.col_start, ix.dev.recs);
+            } else {
+                if (p.mode == VCM_FULL)
+                    hipLaunchKernelGGL((k_blocks<3, NS, VCM_FULL>), grid, dim3(256), 0, s, B, ix.dev.col_start, ix.dev.recs);
+                else
+                    hipLaunchKernelGGL((k_blocks<3, NS, VCM_FRACTION>), grid, dim3(256), 0, s, B, ix.dev.col_start, ix.dev.recs);
+            }
+        };
+        dispatch_blocks<3, 0>(ns, go);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return set_error(VCM_E_DEVICE, std::string("block kernel launch: ") + hipGetErrorString(e));
+    }
+    return VCM_OK;
+}
+
+}  // namespace vcm

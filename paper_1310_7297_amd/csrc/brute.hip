@@ -19,233 +19,10 @@
 #include <cmath>
 #include <type_traits>
 
-#include "vcm_internal.h"
+#include "trace_common.h"
 
 namespace vcm {
 namespace {
-
-constexpr float kWalkMargin = 1.0f / 128.0f;
-constexpr float kLambdaMargin = 1e-6f;
-
-// Exact contact of the closed segment [q, s] with the closed box [lo, hi],
-// given d = s - q, lq = lo - q and hq = hi - q.  All coordinates are
-// multiples of 2^-8 below 2^14, so these differences are exact in float32
-// and every product of two of them is exact in float64.  Along each axis the
-// box admits the ray parameters between an entry and an exit fraction
-// (numerator / positive denominator); the segment meets the box iff no entry
-// exceeds an exit, the bounds 0 and 1 included, compared by cross-multiplying.
-template <int DIM>
-__device__ __attribute__((always_inline)) inline bool exact_contact(const float *d,
-                                                                    const float *lq,
-                                                                    const float *hq) {
-    float en[DIM], ex[DIM], de[DIM];
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        const bool up = d[k] > 0.0f, down = d[k] < 0.0f;
-        en[k] = up ? lq[k] : (down ? -hq[k] : 0.0f);
-        ex[k] = up ? hq[k] : (down ? -lq[k] : 1.0f);
-        de[k] = up ? d[k] : (down ? -d[k] : 1.0f);
-        // a direction component of 0: q itself must lie in the slab
-        ok = ok && (up || down || (lq[k] <= 0.0f && hq[k] >= 0.0f));
-        ok = ok && en[k] <= de[k] && ex[k] >= 0.0f;
-    }
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-#pragma unroll
-        for (int b = 0; b < DIM; ++b)
-            if (a != b)
-                ok = ok && double(en[a]) * double(de[b]) <= double(ex[b]) * double(de[a]);
-    return ok;
-}
-
-__device__ inline unsigned long long ballot(bool p) { return __ballot(p); }
-
-template <typename R>
-__device__ inline R my_atan2(R y, R x);
-template <>
-__device__ inline float my_atan2<float>(float y, float x) { return atan2f(y, x); }
-template <>
-__device__ inline double my_atan2<double>(double y, double x) { return atan2(y, x); }
-template <typename R>
-__device__ inline R my_atan(R x);
-template <>
-__device__ inline float my_atan<float>(float x) { return atanf(x); }
-template <>
-__device__ inline double my_atan<double>(double x) { return atan(x); }
-
-// Visual angle of the target from q (Eq. 1 with the oblique size of Eq. 2),
-// divided by its largest value V0.  alpha is measured in the meridian plane:
-// h = |Delta . n|, rho = |Delta - (Delta . n) n|, alpha = atan2(h, rho).
-template <int DIM, typename R>
-__device__ inline R raw_colour(const TargetDesc &T, const ParamDesc &P, const float *q) {
-    R dl[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) dl[k] = (k < DIM) ? R(q[k]) - R(T.c[k]) : R(0);
-    int nax = T.nax;
-    if (T.kind == VCM_CUBE) {
-        nax = 0;
-        if (fabs(dl[1]) > fabs(dl[nax])) nax = 1;
-        if (fabs(dl[2]) > fabs(dl[nax])) nax = 2;
-    }
-    R h = fabs(dl[nax]);
-    R r2 = R(0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        if (k != nax) r2 += dl[k] * dl[k];
-    const R rho = sqrt(r2);
-    const R D = sqrt(r2 + h * h);
-    const R alpha = my_atan2<R>(h, rho);
-    const R Sa = alpha * (R(2) / R(M_PI)) * R(T.S);
-    const R Dn = D > R(P.d0) ? D : R(P.d0);
-    const R V = R(2) * my_atan<R>(Sa / (R(2) * Dn));
-    return V / R(P.V0);
-}
-
-// Field of view (closed wedge about the normal, apex at the target centre).
-// The quantities are exact in float64 for inputs on the 2^-8 lattice.
-template <int DIM>
-__device__ inline bool in_fov(const TargetDesc &T, const ParamDesc &P, const float *q) {
-    if (P.fov_kind == kFovAll) return true;
-    double d2 = 0.0, dn = 0.0;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        const double d = double(q[k]) - double(T.c[k]);
-        d2 += d * d;
-        if (k == T.nax) dn = T.nsign * d;
-    }
-    if (P.fov_kind == kFovHalf) return dn >= 0.0;
-    if (P.fov_kind == kFovNarrow) return dn >= 0.0 && dn * dn >= P.fov_c2 * d2;
-    return dn >= 0.0 || dn * dn <= P.fov_c2 * d2;
-}
-
-
-__device__ inline float readlane_f(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ inline unsigned long long lanes_below() {
-    return (1ull << (threadIdx.x & 63)) - 1ull;
-}
-__device__ inline int mbcnt(unsigned long long m) {
-    return __builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(m >> 32),
-                                     __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(m), 0u));
-}
-
-// A wave-uniform float as a scalar-register value.
-__device__ inline float uniform_f(float x) {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
-}
-
-// Position of local sample w (lattice index u fastest) of the facet with face
-// code fc (cube: 2k for the face at -k, 2k+1 for +k; other targets: their one
-// facet, fc ignored).
-template <int DIM>
-__device__ __attribute__((always_inline)) inline void sample_pos_face(const TargetDesc &T, unsigned fc_u,
-                                                                      unsigned w, float *s) {
-    const unsigned iv = static_cast<unsigned>((w * T.m_su) >> 32);
-    const unsigned iu = w - iv * T.su;
-    const float u = static_cast<float>(2 * static_cast<int>(iu) + 1 - T.su) * T.hu;
-    const float v = static_cast<float>(2 * static_cast<int>(iv) + 1 - T.sv) * T.hv;
-    s[0] = T.c[0];
-    s[1] = T.c[1];
-    s[2] = DIM == 3 ? T.c[2] : 0.0f;
-    if (T.kind == VCM_CUBE) {
-        const int fc = static_cast<int>(fc_u);
-        const int k = fc >> 1;
-        const int ua = (k == 0) ? 1 : 0;
-        // k may differ between lanes: select among scalar copies (values, not
-        // loads, so the selection does not become a per-lane memory load)
-        const float c0 = uniform_f(T.c[0]), c1 = uniform_f(T.c[1]), c2 = uniform_f(T.c[2]);
-        const float h0 = uniform_f(T.half[0]), h1 = uniform_f(T.half[1]), h2 = uniform_f(T.half[2]);
-        const float ck = k == 0 ? c0 : (k == 1 ? c1 : c2);
-        const float hk = k == 0 ? h0 : (k == 1 ? h1 : h2);
-        const float plane = (fc & 1) ? ck + hk : ck - hk;
-        s[0] = k == 0 ? plane : (ua == 0 ? c0 + u : s[0]);
-        s[1] = k == 1 ? plane : (ua == 1 ? c1 + u : c1 + v);
-        s[2] = k == 2 ? plane : c2 + v;
-    } else {
-        const int wax = 1 - T.nax;
-        if (wax == 0) s[0] = T.c[0] + u;
-        else s[1] = T.c[1] + u;
-        if (T.kind == VCM_BILLBOARD) s[2] = T.c[2] + v;
-    }
-}
-
-// Sample table of a launch: every sample of every facet (the cube's six faces
-// or the one facet), indexed by face code * per_facet + local index, in LDS.
-// A cube has at most 128 samples per face (three faces of live samples fit
-// the 384 ray slots), other targets at most 384: 768 entries.
-constexpr int kTableMax = 768;
-
-template <int DIM>
-__device__ void build_sample_table(const TargetDesc &T, float4 *tab) {
-    const int n = (T.kind == VCM_CUBE ? 6 : 1) * T.per_facet;
-    for (int t = threadIdx.x; t < n && t < kTableMax; t += blockDim.x) {
-        const unsigned fc = static_cast<unsigned>((static_cast<unsigned>(t) * T.m_pf) >> 32);
-        const unsigned w = static_cast<unsigned>(t) - fc * T.per_facet;
-        float sp[3];
-        sample_pos_face<DIM>(T, fc, w, sp);
-        tab[t] = make_float4(sp[0], sp[1], sp[2], 0.0f);
-    }
-    __syncthreads();
-}
-
-// Sample sources: lattice arithmetic, or the workgroup's table.
-constexpr int kTabNone = 0, kTabBlock = 1;
-
-// Position of sample `si` among the live samples of a viewpoint whose live
-// facets are `faces` (cube, packed 4 bits per live face) or the single facet
-// (segment, billboard); from the sample table when one is given.
-template <int DIM, int TAB>
-__device__ __attribute__((always_inline)) inline void sample_pos(const TargetDesc &T, unsigned faces, unsigned si,
-                                                                 float *s, const void *tab) {
-    const unsigned f = static_cast<unsigned>((si * T.m_pf) >> 32);
-    const unsigned w = si - f * T.per_facet;
-    const unsigned fc = T.kind == VCM_CUBE ? (faces >> (4 * f)) & 7u : 0u;
-    if (TAB == kTabBlock) {
-        const float4 p = static_cast<const float4 *>(tab)[fc * T.per_facet + w];
-        s[0] = p.x;
-        s[1] = p.y;
-        s[2] = p.z;
-    } else {
-        sample_pos_face<DIM>(T, fc, w, s);
-    }
-}
-
-// Rays of one slot: sample position and reciprocal direction per lane.  A
-// zero direction component gets reciprocal 0 and sends the lane's tests to
-// the exact predicate (zero_lane).
-template <int DIM, int TAB>
-__device__ __attribute__((always_inline)) inline bool ray_setup(const TargetDesc &T, unsigned faces, const float *q,
-                                                               unsigned si, float *s, float *inv,
-                                                               const void *tab) {
-    sample_pos<DIM, TAB>(T, faces, si, s, tab);
-    bool zero = false;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const float d = s[k] - q[k];
-        // v_rcp_f32 is accurate to 1 ulp; with the exact numerator lo - q the
-        // slab parameter carries at most 1.5 * 2^-23 relative error.
-        inv[k] = (k < DIM && d != 0.0f) ? __builtin_amdgcn_rcpf(d) : 0.0f;
-        zero = zero || (k < DIM && d == 0.0f);
-    }
-    return zero;
-}
-
-// Float32 slab test: gap t1 - t0 of the parameter interval [t0, t1] that the
-// box cuts from [0, 1]; the segment meets the box iff gap >= 0.
-template <int DIM>
-__device__ inline float slab_gap(const float *inv, const float *lq, const float *hq) {
-    float t0 = 0.0f, t1 = 1.0f;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        const float a = lq[k] * inv[k];
-        const float b = hq[k] * inv[k];
-        t0 = fmaxf(t0, fminf(a, b));
-        t1 = fminf(t1, fmaxf(a, b));
-    }
-    return t1 - t0;
-}
 
 struct WaveStats {
     unsigned long long tests = 0, slots = 0, rechecks = 0, cols = 0, rays = 0, inside = 0, recs = 0, narrow = 0;
@@ -259,21 +36,6 @@ struct WaveStats {
 template <int NS>
 using RaySlot = typename std::conditional<(NS <= 3), float4, int>::type;
 
-// A non-negative float as an unsigned integer with the same order; negative
-// values (and -0) map to 0, below every box coordinate of the index frame.
-__device__ inline unsigned ord(float x) { return x > 0.0f ? __float_as_uint(x) : 0u; }
-
-// The index is immutable while kernels run: read it through the constant
-// address space, so that wave-uniform reads (column offsets, the blocker
-// cache's record) become scalar loads.
-// (The host pass of the compiler only needs the declarations.)
-#if defined(__HIP_DEVICE_COMPILE__)
-#define VCM_CONST __attribute__((address_space(4)))
-#else
-#define VCM_CONST
-#endif
-typedef const VCM_CONST int32_t *cptr_i32;
-typedef const VCM_CONST BoxRec *cptr_rec;
 
 // Rays of slot j (among the open ones) that a box blocks: float32 slab test
 // with margin eps; results inside the margin, and rays with a zero direction
@@ -908,6 +670,89 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE
     flush_stats<STATS>(B.stats, ws, n_disagree);
 }
 
+// The undecided smallest blocks of the visible-region tree (blocks.hip): each
+// takes the gate of its representative viewpoint -- the lowest-index centre
+// viewpoint of the block -- traced like any viewpoint, for all the
+// viewpoints it holds.  One wavefront per block.
+struct LeafArgs {
+    const uint32_t *list;   // blocks (index in the leaf level's block grid)
+    const unsigned *count;  // entries of list
+    unsigned *claim;        // work counter (cleared)
+    int32_t side;           // viewpoints per block edge
+    int32_t nb[3];          // blocks per axis
+};
+
+template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE>, 8))) void k_leaves(
+    BruteArgs A, const int32_t *col_start_g, const BoxRec *recs_g, LeafArgs LA) {
+    const cptr_i32 col_start = (cptr_i32)col_start_g;
+    const cptr_rec recs = (cptr_rec)recs_g;
+    __shared__ RaySlot<NS> lds_rays[4][NS * 64];
+    __shared__ float4 s_tab[kTableMax];
+    build_sample_table<DIM>(A.tgt, s_tab);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    RaySlot<NS> *lds = lds_rays[wave];
+    const int lane = threadIdx.x & 63;
+    const TargetDesc &T = A.tgt;
+    const ParamDesc &P = A.prm;
+    WaveStats ws;
+    unsigned long long n_disagree = 0, n_leaves = 0;
+    const unsigned n_in = *LA.count;
+    for (;;) {
+        unsigned item = 0;
+        if (lane == 0) item = atomicAdd(LA.claim, 1u);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
+        if (item >= n_in) break;
+        const uint32_t b = LA.list[item];
+        const int bi[3] = {static_cast<int>(b % static_cast<uint32_t>(LA.nb[0])),
+                           static_cast<int>((b / static_cast<uint32_t>(LA.nb[0])) % static_cast<uint32_t>(LA.nb[1])),
+                           static_cast<int>(b / (static_cast<uint32_t>(LA.nb[0]) * static_cast<uint32_t>(LA.nb[1])))};
+        int lo[3], hi[3];
+        float q[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = k < DIM ? bi[k] * LA.side : 0;
+            hi[k] = k < DIM ? min(lo[k] + LA.side, A.grid.n[k]) - 1 : 0;
+            const int r = lo[k] + min((LA.side - 1) / 2, hi[k] - lo[k]);
+            q[k] = k < DIM ? uniform_f(A.grid.o[k] + static_cast<float>(2 * r + 1) * A.grid.h2[k]) : 0.0f;
+        }
+        unsigned faces = 0;
+        int nf = 0;
+        if (T.kind == VCM_CUBE) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const bool up = q[k] > T.c[k] + T.half[k];
+                const bool dn = q[k] < T.c[k] - T.half[k];
+                if (up || dn) {
+                    faces |= static_cast<unsigned>(2 * k + (up ? 1 : 0)) << (4 * nf);
+                    ++nf;
+                }
+            }
+        } else {
+            nf = 1;
+        }
+        const int N = nf * T.per_facet;
+        const bool fov = in_fov<DIM>(T, P, q);
+        int cnt = 0;
+        if (fov && N > 0) {
+            if (STATS) ws.rays += N;
+            int blk = -1;
+            const int vis = trace_viewpoint<DIM, NS, EXACT64, MODE, STATS, kTabBlock>(
+                A, col_start, recs, q, faces, N, lds, s_tab, blk, ws, n_disagree);
+            cnt = MODE == VCM_FRACTION ? vis : (vis == N ? N : 0);
+        }
+        ++n_leaves;
+        const uint32_t word = static_cast<uint32_t>(cnt) | (static_cast<uint32_t>(N) << 10) | (fov ? (1u << 20) : 0u);
+        const int e0 = hi[0] - lo[0] + 1, e1 = hi[1] - lo[1] + 1, e2 = hi[2] - lo[2] + 1;
+        for (int t = lane; t < e0 * e1 * e2; t += 64) {
+            const int i = lo[0] + t % e0, j = lo[1] + (t / e0) % e1, k = lo[2] + t / (e0 * e1);
+            A.gate[i + static_cast<int64_t>(A.grid.n[0]) * (j + static_cast<int64_t>(A.grid.n[1]) * k)] = word;
+        }
+    }
+    flush_stats<STATS>(A.stats, ws, n_disagree);
+    if (STATS && lane == 0) atomicAdd(&A.stats->leaves, n_leaves);
+}
+
 __global__ void k_zero_counter(unsigned *c) {
     if (threadIdx.x < kXcd) c[threadIdx.x * kCtrStride] = 0u;
 }
@@ -1030,6 +875,35 @@ vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, cons
         using V = decltype(v);
         hipLaunchKernelGGL((k_brute_batch<V::DIM, V::NS, V::E, V::MODE, V::ST>), grid, dim3(256), 0, s, b,
                            d_recs, d_group_end, ix.dev.col_start, ix.dev.recs);
+    });
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(VCM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return VCM_OK;
+}
+
+vcm_status launch_leaves(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
+                         const BlockPlan &bp, uint32_t *gate, const uint32_t *list, const unsigned *count,
+                         unsigned *claim, hipStream_t s, DevStats *stats) {
+    if (g.count <= 0) return VCM_OK;
+    BruteArgs a = make_brute_args(ix, t, g, p, vcm_result{}, nullptr, 1, 1);
+    a.gate = gate;
+    a.stats = stats;
+    const int ns = slots_for(t);
+    if (ns < 1 || ns > kMaxSlots) return set_error(VCM_E_INVALID, "too many target samples");
+    LeafArgs la{};
+    la.list = list;
+    la.count = count;
+    la.claim = claim;
+    la.side = bp.leaf;
+    for (int k = 0; k < 3; ++k) la.nb[k] = k < ix.dim ? (g.n[k] + bp.leaf - 1) / bp.leaf : 1;
+    const int64_t nleaf = bp.count[bp.levels - 1];
+    const dim3 grid(static_cast<unsigned>(
+        std::max<int64_t>(1, std::min<int64_t>((nleaf + 3) / 4, int64_t(device_cus(ix.device)) * 8))));
+    // slot counts rounded up to 2, 3 or 6, as for batches (fewer instances)
+    dispatch<true>(ix.dim, p.fp64 != 0, ns, p.mode, stats != nullptr, [&](auto v) {
+        using V = decltype(v);
+        hipLaunchKernelGGL((k_leaves<V::DIM, V::NS, V::E, V::MODE, V::ST>), grid, dim3(256), 0, s, a,
+                           a.idx.col_start, a.idx.recs, la);
     });
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(VCM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));

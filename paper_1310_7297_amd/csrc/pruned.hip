@@ -10,7 +10,8 @@
 // comparing against the boundary values themselves, which are evaluated in
 // float64 with the same expressions that define them.  One thread per
 // viewpoint; the gate (visible count, live samples, field of view) comes
-// from the ray-casting kernel run at the block representatives.
+// from the visible-region blocks (blocks.hip) or, for the undecided
+// smallest blocks, from the ray kernel at their representatives.
 #include <cmath>
 
 #include "vcm_internal.h"
@@ -20,7 +21,8 @@ namespace {
 
 struct CellFrame {
     double S, mu, d0, V0, dmax;
-    int K;  // rings 0..K; ring K ends at dmax
+    int K;           // rings 0..K; ring K ends at dmax
+    int rings_only;  // viewer-centric maps: one band per ring, colour facing
 };
 
 // Boundary radius d_i (d_0 = near point, d_{K+1} = d_max).
@@ -81,7 +83,7 @@ __device__ inline Ring make_ring(const CellFrame &F, int i) {
     int L = max(0, static_cast<int>(floor((r.W0 - F.mu) / F.mu)));
     while (r.W0 - (L + 1) * F.mu >= F.mu) ++L;
     while (L > 0 && r.W0 - L * F.mu < F.mu) --L;
-    r.L = L;
+    r.L = F.rings_only ? 0 : L;
     return r;
 }
 
@@ -104,7 +106,7 @@ __device__ inline int band_of(const CellFrame &F, const Ring &r, double alpha) {
 }
 
 __device__ inline double cell_colour(const CellFrame &F, const Ring &r, int j) {
-    const double gm = 0.5 * (gamma_of(F, r, j) + gamma_of(F, r, j + 1));
+    const double gm = F.rings_only ? M_PI / 2.0 : 0.5 * (gamma_of(F, r, j) + gamma_of(F, r, j + 1));
     return vis_angle(F.S, r.dp, gm) / F.V0;
 }
 
@@ -146,10 +148,8 @@ struct PrunedArgs {
     TargetDesc tgt;
     GridDesc grid;
     ParamDesc prm;
-    const uint32_t *gate;  // per representative: count | N << 10 | fov << 20
-    int32_t theta;
+    const uint32_t *gate;  // per viewpoint: count | N << 10 | fov << 20
     int32_t method;        // VCM_PRUNED_E / M / T
-    int32_t gn[3];         // representative grid
     int32_t dim;
     uint8_t *bin;
     float *c;
@@ -258,14 +258,9 @@ __device__ void colour_viewpoint(const PrunedArgs &A, int64_t vp, PrunedSums &su
     const double alpha = atan2(h, sqrt(r2));
     const double rho = D * cos(alpha), hh = D * sin(alpha);
 
-    // gate of the block representative
-    int64_t rep = 0;
-    {
-        int b[3];
-        for (int k = 0; k < 3; ++k) b[k] = (k < A.dim) ? ii[k] / A.theta : 0;
-        rep = b[0] + static_cast<int64_t>(A.gn[0]) * (b[1] + static_cast<int64_t>(A.gn[1]) * b[2]);
-    }
-    const uint32_t gw = A.gate[rep];
+    // the viewpoint's gate: from its decided block, or its smallest block's
+    // representative
+    const uint32_t gw = A.gate[vp];
     const int vis = static_cast<int>(gw & 1023u), N = static_cast<int>((gw >> 10) & 1023u);
     const bool fov = (gw >> 20) & 1u;
     const bool shown = fov && N > 0 && vis > 0;   // some colour survives the gate
@@ -287,7 +282,8 @@ __device__ void colour_viewpoint(const PrunedArgs &A, int64_t vp, PrunedSums &su
     if (A.sums) {
         // reference colour under the same gate: the brute-force measure for
         // VCM_E, q's own cell for VCM_M and VCM_T
-        const double ref_raw = A.method == VCM_PRUNED_E ? vis_angle(F.S, D > F.d0 ? D : F.d0, alpha) / F.V0 : ce;
+        const double am = F.rings_only ? M_PI / 2.0 : alpha;  // a viewer's points face it
+        const double ref_raw = A.method == VCM_PRUNED_E ? vis_angle(F.S, D > F.d0 ? D : F.d0, am) / F.V0 : ce;
         const double ref = gatef * ref_raw;
         sum.d[0] += ref - col;
         sum.d[1] += fabs(ref - col);
@@ -329,9 +325,8 @@ int count_rings(double S, double mu, double d0, double *V0) {
 }
 
 vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g,
-                         const ParamDesc &p, int method, int theta, const uint32_t *gate,
-                         const int32_t gn[3], const vcm_result &r, hipStream_t stream,
-                         unsigned long long *fallback, double *sums) {
+                         const ParamDesc &p, int method, const uint32_t *gate, const vcm_result &r,
+                         hipStream_t stream, unsigned long long *fallback, double *sums) {
     PrunedArgs a{};
     double V0;
     const double mu = p.mu_d;
@@ -341,13 +336,12 @@ vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g
     a.F.K = count_rings(t.S, mu, p.d0_d, &V0);
     a.F.V0 = V0;
     a.F.dmax = t.S / (2.0 * std::tan(mu / 2.0));
+    a.F.rings_only = t.kind == VCM_VIEWER ? 1 : 0;
     a.tgt = t;
     a.grid = g;
     a.prm = p;
     a.gate = gate;
-    a.theta = theta;
     a.method = method;
-    for (int k = 0; k < 3; ++k) a.gn[k] = gn[k];
     a.dim = ix.dim;
     a.bin = r.bin;
     a.c = r.c;

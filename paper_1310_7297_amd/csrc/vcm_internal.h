@@ -68,7 +68,7 @@ struct TargetDesc {
     float half[3];      // half extents of the target's bounding box
     float hu, hv;       // half lattice spacing along u and v
     float S;            // size entering Eq. 1
-    float pad;
+    float rmax;         // viewer: radius of the covered ball (d_max); else 0
 };
 
 // Viewpoint lattice: q = o + (2i + 1) h2 (exact in float32).
@@ -116,6 +116,10 @@ struct DevStats {
     unsigned long long t_fallbacks;
     unsigned long long records;
     unsigned long long narrow_tests;
+    unsigned long long blocks;          // visible-region blocks classified
+    unsigned long long blocks_decided;  // of which decided as a whole
+    unsigned long long hull_tests;      // sample x obstacle hull tests of the blocks
+    unsigned long long leaves;          // undecided smallest blocks traced at their representative
 };
 
 // Everything one brute-force launch needs (passed by value).
@@ -221,14 +225,45 @@ vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, cons
                               const BruteArgs *d_recs, const uint32_t *d_group_end, int blocks,
                               hipStream_t s);
 
-// Pruned colouring (E / M / T) of every viewpoint from the block gates.
+// Visible-region tree of the pruned methods (blocks.hip): blocks of `side`
+// viewpoints per edge, from the root side down to the leaf side (the
+// largest power of two not above theta), halved at every level.
+constexpr int kRootBlockSide = 8;
+constexpr int kMaxBlockLevels = 8;
+struct BlockPlan {
+    int leaf = 1, root = 1, levels = 0;
+    int side[kMaxBlockLevels] = {};
+    int64_t count[kMaxBlockLevels] = {};  // blocks of the level over the grid
+};
+int block_leaf_side(int theta);
+BlockPlan block_plan(const GridDesc &g, int dim, int theta);
+// Levels the block kernel classifies: all, or all but the single-viewpoint
+// level, whose blocks go to the ray kernel unclassified.  The undecided
+// smallest blocks are then lists[block_classified_levels(bp)].
+int block_classified_levels(const BlockPlan &bp);
+// Classify the tree's blocks level by level.  gate: one word per viewpoint,
+// written for the viewpoints of decided blocks; lists[l] (l = 1..levels)
+// receive the blocks of level l (lists[levels]: the undecided smallest
+// blocks), each with room for bp.count[min(l, levels - 1)] entries; ctr:
+// 2 (levels + 1) words (entry counts of the lists at ctr[l], work counters
+// after them), cleared by the call.
+vcm_status launch_blocks(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
+                         const BlockPlan &bp, uint32_t *gate, uint32_t *const *lists, unsigned *ctr,
+                         hipStream_t s, DevStats *stats);
+// The undecided smallest blocks (list, with its entry count at *count):
+// each takes its representative viewpoint's traced gate for every viewpoint
+// it holds.  claim: a work counter, cleared by launch_blocks.
+vcm_status launch_leaves(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
+                         const BlockPlan &bp, uint32_t *gate, const uint32_t *list, const unsigned *count,
+                         unsigned *claim, hipStream_t s, DevStats *stats);
+
+// Pruned colouring (E / M / T) of every viewpoint from its gate word.
 // With `sums` non-null (pruned_sum_blocks(g) x kPrunedSums doubles), each
 // workgroup also writes its partial sums of the Sec. V-A error and of the
 // Sec. IV-A measured error (see pruned.hip).
 vcm_status launch_pruned(const Index &ix, const TargetDesc &t, const GridDesc &g,
-                         const ParamDesc &p, int method, int theta, const uint32_t *gate,
-                         const int32_t gn[3], const vcm_result &r, hipStream_t stream,
-                         unsigned long long *fallback, double *sums);
+                         const ParamDesc &p, int method, const uint32_t *gate, const vcm_result &r,
+                         hipStream_t stream, unsigned long long *fallback, double *sums);
 int64_t pruned_sum_blocks(const GridDesc &g);
 int count_rings(double S, double mu, double d0, double *V0);
 
@@ -240,17 +275,21 @@ void error_bounds(double S, double mu, double d0, int dim, double *out);
 // block gates, and (pruned methods with statistics) the colouring's partial
 // sums.
 struct WsLayout {
-    size_t counter = 0, gate = 0, sums = 0, bytes = 0;
+    size_t counter = 0, gate = 0, sums = 0, ctr = 0, bytes = 0;
+    size_t lists[kMaxBlockLevels + 1] = {};
+    BlockPlan plan;
     int64_t n_sums = 0;  // workgroups writing PrunedSums (0: none)
 };
-WsLayout query_workspace(const GridDesc &g, int method, int theta, bool stats);
+WsLayout query_workspace(const GridDesc &g, int dim, int method, int theta, bool sums);
 
-// One query on one stream: brute force, or gates plus pruned colouring.
-// `ws` is device memory laid out as query_workspace(g, method, theta,
-// stats != nullptr), 256-byte aligned; its contents on entry do not matter.
+// One query on one stream: brute force, or the visible-region blocks, their
+// undecided smallest blocks' representatives, and the pruned colouring.
+// `ws` is device memory laid out as query_workspace(g, dim, method, theta,
+// sums), 256-byte aligned; its contents on entry do not matter.  With `sums`
+// (pruned methods) the colouring leaves its partial sums there.
 vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
                      int method, int theta, const vcm_result &r, hipStream_t s, DevStats *stats,
-                     char *ws);
+                     char *ws, bool sums);
 
 // Pinned host buffers for host-to-device uploads, reused once the copies
 // that read them have completed (tracked by an event per buffer).
@@ -286,9 +325,7 @@ struct PlanQuery {
     int theta;
     vcm_result r;
     int ns;
-    int32_t gn[3];   // block grid (pruned methods)
-    int64_t nrep;    // blocks
-    size_t gate_off; // byte offset of the block gates in the plan's buffer
+    size_t ws_off;   // pruned methods: byte offset of the query's workspace in the plan's buffer
 };
 
 // Queries that share one persistent launch.
@@ -302,8 +339,8 @@ struct PlanGroup {
 };
 
 // Device layout and launch sequence of a batch:
-//   per group: BruteArgs[members] | item ends[members] | kXcd counters,
-//   then per pruned query its block gates.
+//   per group of brute-force queries: BruteArgs[members] | item ends[members]
+//   | kXcd counters, then per pruned query its workspace (run_query).
 struct BatchPlan {
     const Index *ix = nullptr;
     int device = 0;

@@ -13,7 +13,7 @@ import paper_1310_7297_amd as vcm
 from paper_1310_7297_amd import scenes
 from paper_1310_7297_amd.scenes import (BILLBOARD, BIN_LOG, CUBE, FRACTION, FULL, SEGMENT, Grid,
                                          Params, Query, Scene, Target)
-from parity import near_edge
+from parity import compare_pruned, near_edge
 
 pytestmark = pytest.mark.gpu
 METHOD = {1: "E", 2: "M", 3: "T"}
@@ -37,46 +37,6 @@ def _gpu_map(scene, query):
     return out
 
 
-def _target_size(t):
-    return max(t.size[0], t.size[1]) if t.kind == BILLBOARD else t.size[0]
-
-
-def compare_pruned(gpu, orc, scene, query, vp, method):
-    """counts exact; colours within 1e-5 relative except at cell-boundary ties."""
-    n_bins = query.params.n_bins
-    g_cnt = gpu["count"][vp].astype(np.int64)
-    assert np.array_equal(g_cnt, orc["count"].astype(np.int64)), "gate counts differ"
-    gc = gpu["c"][vp].astype(np.float64)
-    oc = orc["c"]
-    bad = np.nonzero(np.abs(gc - oc) > 1e-5 * np.abs(oc) + 1e-9)[0]
-    ties = 0
-    if len(bad):
-        t = query.target
-        mu = query.params.mu_arcmin / 60 * math.pi / 180
-        cells = oracle.Cells(_target_size(t), mu, query.params.near_d0)
-        pts = oracle.viewpoint_coords(query.grid, vp[bad])
-        for b, qpt in zip(bad, pts):
-            D, a = oracle.meridian(t, qpt)
-            base = cells.colours(D, a)[METHOD[method]]
-            assert oc[b] > 0 and base > 0, (b, gc[b], oc[b])
-            gate = oc[b] / base
-            ok = False
-            for dd, da in ((1 + 1e-9, 0), (1 - 1e-9, 0), (1, 1e-9), (1, -1e-9)):
-                alt = cells.colours(D * dd, min(max(a + da, 0.0), math.pi / 2))[METHOD[method]]
-                if abs(gc[b] - gate * alt) <= 1e-5 * abs(gc[b]) + 1e-9:
-                    ok = True
-                    break
-            assert ok, f"viewpoint {vp[b]}: gpu {gc[b]} oracle {oc[b]} (D {D}, alpha {a})"
-            ties += 1
-    assert ties <= max(2, 1e-3 * len(vp)), ties
-    tie = np.zeros(len(vp), bool)
-    tie[bad] = True
-    edge = near_edge(orc["cb"], n_bins)
-    badb = np.nonzero((gpu["bin"][vp] != orc["bin"]) & ~edge & ~tie)[0]
-    assert badb.size == 0, f"bins differ at {vp[badb[:5]]}"
-    return ties
-
-
 @pytest.mark.parametrize("method", [1, 2, 3])
 @pytest.mark.parametrize("mode", [FULL, FRACTION])
 @pytest.mark.parametrize("theta", [1, 3])
@@ -95,26 +55,36 @@ def test_plain2d_full_map(method, mode, theta):
 
 @pytest.mark.parametrize("method", [1, 2, 3])
 @pytest.mark.parametrize("kind", [BILLBOARD, CUBE])
-def test_small_3d_full_map(method, kind):
+@pytest.mark.parametrize("theta", [1, 2, 4])
+@pytest.mark.parametrize("mode", [FULL, FRACTION])
+def test_small_3d_full_map(method, kind, theta, mode):
+    """Whole maps against the oracle, the visible-region blocks included:
+    the same blocks are decided, the undecided smallest ones take their
+    representative's gate."""
     if kind == CUBE:
         t = Target(CUBE, (64.0, 64.0, 4.0), (8.0, 0.0), samples_u=4, samples_v=4)
     else:
         t = Target(BILLBOARD, (64.0, 64.0, 6.0), (8.0, 4.0), normal_axis=0, samples_u=8, samples_v=4)
     scene = scenes.city(128.0, 40, seed=11, side=(4.0, 16.0), targets=[t], clearance=2.0)
     scene = Scene(3, scene.lo, np.vstack([scene.hi[:2], np.minimum(scene.hi[2], 12.0)]))
-    g = Grid((0.0, 0.0, 0.0), (128.0, 128.0, 32.0), (32, 32, 8))
-    q = Query(t, g, Params(n_bins=16, method=method, mode=FRACTION, bin_scale=BIN_LOG))
+    # ragged: 30 x 29 x 7 viewpoints cut the blocks at the grid's end
+    g = Grid((0.0, 0.0, 0.0), (120.0, 116.0, 28.0), (30, 29, 7))
+    q = Query(t, g, Params(n_bins=16, method=method, mode=mode, bin_scale=BIN_LOG, theta_blocks=theta))
     gm = _gpu_map(scene, q)
     vp = np.arange(g.count, dtype=np.int64)
-    o = oracle.vcm_eval_pruned(scene, q, method, 1, vp)
+    o = oracle.vcm_eval_pruned(scene, q, method, theta, vp, nthreads=8)
     compare_pruned(gm, o, scene, q, vp, method)
     assert (o["count"] > 0).sum() > 100
+    st = gm["stats"]
+    assert st["blocks_decided"] > 0 and st["blocks"] >= st["blocks_decided"]
+    # every undecided smallest block is traced once at its representative
+    assert st["leaves"] > 0
 
 
-@pytest.mark.parametrize("method", [1, 2, 3])
-def test_city4km_cube_sampled(method):
+@pytest.mark.parametrize("method,theta", [(1, 1), (2, 1), (3, 1), (1, 2), (1, 4), (2, 4)])
+def test_city4km_cube_sampled(method, theta):
     scene, q = scenes.city4km_cube()
-    q = _with(q, method=method, mode=FULL)
+    q = _with(q, method=method, mode=FULL, theta_blocks=theta)
     g = _gpu_map(scene, q)
     rng = np.random.default_rng(7)
     vp = np.unique(np.concatenate([scenes.viewpoint_sample(q.grid, 150, 7),
@@ -127,19 +97,24 @@ def test_city4km_cube_sampled(method):
             for k in (2, 6, 12, 20, 40):
                 near.append(i + n[0] * (j + n[1] * k))
     vp = np.unique(np.concatenate([vp, np.array(near, dtype=np.int64)]))
-    o = oracle.vcm_eval_pruned(scene, q, method, 1, vp, nthreads=16)
+    o = oracle.vcm_eval_pruned(scene, q, method, theta, vp, nthreads=16)
     compare_pruned(g, o, scene, q, vp, method)
     assert (o["count"] > 0).sum() >= 10
 
 
-def test_pruned_gate_matches_brute_map():
-    """theta = 1: the pruned methods' visibility gate is the brute force's."""
-    scene, q = scenes.city2km_billboard()
-    q = _with(q, mode=FRACTION)
+@pytest.mark.parametrize("mode", [FULL, FRACTION])
+@pytest.mark.parametrize("cfg", ["city2km_billboard", "city4km_cube"])
+def test_pruned_gate_matches_brute_map(cfg, mode):
+    """theta = 1: the gate the visible-region blocks and the traced smallest
+    blocks give every viewpoint is the brute force's, over whole maps."""
+    scene, q = getattr(scenes, cfg)()
+    q = _with(q, mode=mode)
     b = _gpu_map(scene, q)
     for m in (1, 2, 3):
         p = _gpu_map(scene, _with(q, method=m))
-        assert np.array_equal(p["count"], b["count"])
+        assert np.array_equal(p["count"], b["count"]), m
+        st = p["stats"]
+        assert st["blocks_decided"] > 0 and st["leaves"] < q.grid.count
 
 
 def test_map_error_matches_oracle():
