@@ -32,7 +32,7 @@ class VoGrid(ctypes.Structure):
 class VoParams(ctypes.Structure):
     _fields_ = [("mu_arcmin", ctypes.c_double), ("d0", ctypes.c_double),
                 ("fov_deg", ctypes.c_double), ("n_bins", ctypes.c_int),
-                ("bin_scale", ctypes.c_int), ("mode", ctypes.c_int)]
+                ("bin_scale", ctypes.c_int), ("mode", ctypes.c_int), ("gaze", ctypes.c_int)]
 
 
 def lib():
@@ -104,6 +104,7 @@ def make_params(p) -> VoParams:
     P.n_bins = int(p.n_bins)
     P.bin_scale = int(p.bin_scale)
     P.mode = int(p.mode)
+    P.gaze = int(getattr(p, "gaze", 0))
     return P
 
 

@@ -83,6 +83,7 @@ typedef struct {
     int n_bins;
     int bin_scale;
     int mode;
+    int gaze;   /* field-of-view axis: 0 = the target's normal, +-(1 + k) = +-axis k */
 } vo_params;
 
 #define VO_PI 3.14159265358979323846
@@ -286,9 +287,24 @@ void vo_measure(const vo_target *t, const vo_params *p, const double *q, double 
 
 /* ----------------------------------------------------------- FOV --------- */
 
+/* Axis and orientation of the field-of-view wedge: the target's normal,
+ * or the gaze direction the query names (incremental processing, Sec. IV-C,
+ * turns the gaze without moving the target). */
+static void wedge_axis(const vo_target *t, const vo_params *p, int *axis, int *sign)
+{
+    if (p->gaze == 0) {
+        *axis = t->normal_axis;
+        *sign = t->normal_sign;
+    } else {
+        *axis = (p->gaze > 0 ? p->gaze : -p->gaze) - 1;
+        *sign = p->gaze > 0 ? 1 : -1;
+    }
+}
+
 /* Is q inside the field of view?  The wedge has its apex at the target
- * centre and is symmetric about the target normal n (viewer-at-target
- * symmetry, Sec. III-A): angle(q - m, n) <= FOV / 2, closed.  The test
+ * centre and is symmetric about the wedge axis n, the target normal or the
+ * gaze (viewer-at-target symmetry, Sec. III-A): angle(q - m, n) <= FOV / 2,
+ * closed.  The test
  * compares (Delta.n)^2 with cos^2(FOV/2) |Delta|^2; cos^2 is an exact rational
  * for the half-angles 30/45/60/120/135/150 degrees (the table's FOVs and 90 /
  * 270 degrees), which makes the comparison exact on the 2^-8 lattice: a point
@@ -303,7 +319,9 @@ static int in_wedge(const vo_target *t, const vo_params *p, const double *q)
         dl[k] = (t->kind == VO_SEGMENT && k == 2) ? 0.0 : q[k] - t->center[k];
         d2 += dl[k] * dl[k];
     }
-    double dn = t->normal_sign * dl[t->normal_axis];
+    int ax, sg;
+    wedge_axis(t, p, &ax, &sg);
+    double dn = sg * dl[ax];
     if (half == 90.0)
         return dn >= 0.0;
     double c2;
@@ -476,7 +494,8 @@ static int check_query(int dim, const vo_target *t, const vo_grid *g, const vo_p
         return -1;
     }
     if (t->kind != VO_CUBE && t->normal_axis != 0 && t->normal_axis != 1) return -1;
-    if (t->kind == VO_CUBE && p->fov_deg < 360.0) return -1;
+    if (t->kind == VO_CUBE && p->fov_deg < 360.0 && p->gaze == 0) return -1;
+    if (p->gaze < -dim || p->gaze > dim) return -1;
     if (!(p->fov_deg > 0.0 && p->fov_deg <= 360.0)) return -1;
     if (!(p->mu_arcmin > 0.0) || !(p->d0 > 0.0)) return -1;
     for (int a = 0; a < dim; ++a) {
@@ -929,9 +948,11 @@ static int fov_class(const vo_target *t, const vo_params *p, int nc, const doubl
         wedge = 1;
     } else {
         int all_in = 1, all_out = 1, all_front = 1, all_back = 1;
+        int ax, sg;
+        wedge_axis(t, p, &ax, &sg);
         for (int c = 0; c < nc; ++c) {
             int in = in_wedge(t, p, cq[c]);
-            double dn = t->normal_sign * (cq[c][t->normal_axis] - t->center[t->normal_axis]);
+            double dn = sg * (cq[c][ax] - t->center[ax]);
             all_in = all_in && in;
             all_out = all_out && !in;
             all_front = all_front && dn >= 0.0;

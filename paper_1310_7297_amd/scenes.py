@@ -125,6 +125,7 @@ class Params:
     mode: int = FULL
     theta_blocks: int = 1
     recheck_eps: float = 2.0 ** -20
+    gaze: int = 0              # field-of-view axis: 0 = the target's normal, +-(1 + k) = +-axis k
 
 
 @dataclasses.dataclass

@@ -235,3 +235,27 @@ def test_rejects_target_meeting_an_obstacle():
                 oracle.vcm_eval(sc, q)
         else:
             oracle.vcm_eval(sc, q)
+
+
+def test_fov_gaze_direction():
+    """The wedge can turn with a gaze direction instead of the target's normal
+    (incremental processing, Sec. IV-C): gaze 0 is the normal itself; a cube
+    takes a field of view below 360 degrees only with a gaze."""
+    t = Target(BILLBOARD, (0.0, 0.0, 5.0), (8.0, 4.0), normal_axis=1, normal_sign=-1, samples_u=8, samples_v=4)
+    rng = np.random.default_rng(7)
+    pts = np.round(rng.uniform(-50, 50, size=(300, 3)) * 4) / 4
+    for fov in (60.0, 120.0, 180.0, 240.0, 300.0):
+        for q in pts:
+            assert oracle.in_fov(t, Params(fov_deg=fov), q) == oracle.in_fov(t, Params(fov_deg=fov, gaze=-2), q)
+    # gaze +z on a cube: within 60 degrees of straight up
+    c = Target(CUBE, (0.0, 0.0, 4.0), (4.0, 0.0), samples_u=2, samples_v=2)
+    p = Params(fov_deg=120.0, gaze=3)
+    assert oracle.in_fov(c, p, (0.0, 0.0, 40.0)) and oracle.in_fov(c, p, (10.0, 0.0, 24.0))
+    assert not oracle.in_fov(c, p, (40.0, 0.0, 4.0)) and not oracle.in_fov(c, p, (0.0, 0.0, -20.0))
+    # tan(60 deg) = sqrt(3): the edge of the wedge has no lattice point; just inside and outside
+    assert oracle.in_fov(c, p, (17.0, 0.0, 14.0)) and not oracle.in_fov(c, p, (18.0, 0.0, 14.0))
+    g = Grid((-16.0, -16.0, 0.0), (32.0, 32.0, 32.0), (4, 4, 4))
+    with pytest.raises(ValueError):
+        oracle.vcm_eval(Scene(3, np.zeros((3, 0)), np.zeros((3, 0))), Query(c, g, Params(fov_deg=120.0)))
+    o = oracle.vcm_eval(Scene(3, np.zeros((3, 0)), np.zeros((3, 0))), Query(c, g, p))
+    assert 0 < o["infov"].sum() < g.count
