@@ -95,6 +95,8 @@ typedef struct {
     double origin[2];
     size_t device_bytes;
     double build_ms;       /* wall time of the build                       */
+    double kernel_ms;      /* device time of the build kernels             */
+    int32_t longest_list;  /* box references in the longest column         */
 } vcm_index_info;
 vcm_status vcm_index_get_info(const vcm_index *index, vcm_index_info *info);
 
@@ -154,7 +156,8 @@ typedef enum { VCM_BIN_LINEAR = 0, VCM_BIN_LOG = 1 } vcm_bin_scale;
 typedef struct {
     double mu_arcmin;      /* angular resolution mu, arcminutes (4)          */
     double near_d0;        /* near-point distance d0, metres (0.25)          */
-    double fov_deg;        /* field of view, (0, 360]; cube targets need 360 */
+    double fov_deg;        /* field of view, (0, 360]; below 360, cube
+                              targets need a gaze                           */
     int32_t n_bins;        /* colour bins B, 2..256                          */
     int32_t bin_scale;     /* vcm_bin_scale                                  */
     int32_t method;        /* vcm_method                                     */
@@ -172,7 +175,11 @@ typedef struct {
                               float64 recheck near the boundary, float32
                               measure; VCM_FP64: every ray test exact in
                               float64 and the measure in float64           */
-    int32_t reserved;
+    int32_t gaze;          /* axis of the field-of-view wedge: 0 = the
+                              target's normal (normal_axis, normal_sign);
+                              +-(1 + k) = the +-k axis (k < dim), which lets
+                              the gaze turn without moving the target
+                              (Sec. IV-C) and gives cubes a wedge           */
 } vcm_params;
 
 typedef enum { VCM_FP32_RECHECK = 0, VCM_FP64 = 1 } vcm_precision;
@@ -405,6 +412,35 @@ vcm_status vcm_server_reset_stats(vcm_server *server);
  * (their buffers untouched), launches in flight are waited for; then the
  * server is released and its tickets with it. */
 vcm_status vcm_server_destroy(vcm_server *server);
+
+/* ------------------------------------------------------ incremental views --- */
+
+/* Incremental processing (Sec. IV-C).  vcm_view_create computes, once, the
+ * visibility of every viewpoint of `query` with the field of view at 360
+ * degrees (the query's fov_deg and gaze are ignored) and keeps it on the
+ * device (4 bytes per viewpoint, 8 for the pruned methods); it blocks until
+ * that is done.  vcm_view_render then colours the query's map for a field of
+ * view of fov_deg about the given gaze (as in vcm_params) into `result`
+ * (device buffers), without tracing a ray: a brute-force map, or a pruned
+ * map with theta_blocks = 1, equals vcm_compute of the query with that field
+ * of view bit for bit.  A pruned map with larger blocks masks every
+ * viewpoint by its own position (vcm_compute would give a smallest block
+ * across the wedge its representative's gate).  Enqueues on `stream`.
+ * Renders of one view may run one after another on one stream; the index
+ * must outlive the view. */
+typedef struct vcm_view vcm_view;
+typedef struct {
+    uint64_t viewpoints;
+    size_t device_bytes;
+    double create_ms;       /* wall time of vcm_view_create                  */
+} vcm_view_info;
+vcm_status vcm_view_create(const vcm_index *index, const vcm_query *query, void *stream,
+                           vcm_view **out);
+vcm_status vcm_view_render(vcm_view *view, double fov_deg, int32_t gaze, const vcm_result *result,
+                           void *stream);
+vcm_status vcm_view_get_info(const vcm_view *view, vcm_view_info *info);
+/* Wait for the device, then release the view. */
+vcm_status vcm_view_destroy(vcm_view *view);
 
 /* Approximation error of Sec. V-A between two colour maps of n viewpoints
  * (caller-owned device buffers, one float each), every viewpoint standing

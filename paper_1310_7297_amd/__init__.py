@@ -32,7 +32,8 @@ EXPORTS = ("vcm_last_error", "vcm_version", "vcm_build_index", "vcm_free_index",
            "vcm_batch_run", "vcm_batch_get_info", "vcm_batch_destroy", "vcm_server_create",
            "vcm_submit", "vcm_poll", "vcm_wait", "vcm_server_drain", "vcm_server_get_stats",
            "vcm_server_reset_stats", "vcm_server_destroy", "vcm_tune_cell_size", "vcm_map_error",
-           "vcm_error_bounds")
+           "vcm_error_bounds", "vcm_view_create", "vcm_view_render", "vcm_view_get_info",
+           "vcm_view_destroy")
 
 
 class VcmError(RuntimeError):
@@ -55,7 +56,8 @@ class vcm_index_info(ctypes.Structure):
     _fields_ = [("n_boxes", ctypes.c_int64), ("n_refs", ctypes.c_int64),
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("cell_size", ctypes.c_double),
                 ("origin", ctypes.c_double * 2), ("device_bytes", ctypes.c_size_t),
-                ("build_ms", ctypes.c_double)]
+                ("build_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("longest_list", ctypes.c_int32)]
 
 
 class vcm_target(ctypes.Structure):
@@ -76,7 +78,7 @@ class vcm_params(ctypes.Structure):
                 ("bin_scale", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("theta_blocks", ctypes.c_int32),
                 ("recheck_eps", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("gaze", ctypes.c_int32)]
 
 
 class vcm_query(ctypes.Structure):
@@ -135,6 +137,11 @@ class vcm_server_stats(ctypes.Structure):
                 ("requests_per_s", ctypes.c_double), ("viewpoints_per_s", ctypes.c_double),
                 ("mem_in_use", ctypes.c_size_t), ("mem_peak", ctypes.c_size_t),
                 ("mem_budget", ctypes.c_size_t)]
+
+
+class vcm_view_info(ctypes.Structure):
+    _fields_ = [("viewpoints", ctypes.c_uint64), ("device_bytes", ctypes.c_size_t),
+                ("create_ms", ctypes.c_double)]
 
 
 class vcm_batch_info(ctypes.Structure):
@@ -200,7 +207,14 @@ def load_library(path: Optional[str] = None):
     L.vcm_tune_cell_size.argtypes = [ctypes.POINTER(vcm_obstacles), ctypes.POINTER(vcm_query),
                                      ctypes.c_int32, ctypes.POINTER(vcm_tune_opts),
                                      ctypes.POINTER(vcm_tune_result)]
-    for name in ("vcm_build_index", "vcm_free_index", "vcm_index_get_info", "vcm_compute",
+    L.vcm_view_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_query), ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_void_p)]
+    L.vcm_view_render.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
+                                  ctypes.POINTER(vcm_result), ctypes.c_void_p]
+    L.vcm_view_get_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_view_info)]
+    L.vcm_view_destroy.argtypes = [ctypes.c_void_p]
+    for name in ("vcm_view_create", "vcm_view_render", "vcm_view_get_info", "vcm_view_destroy",
+                 "vcm_build_index", "vcm_free_index", "vcm_index_get_info", "vcm_compute",
                  "vcm_compute_noalloc",
                  "vcm_compute_batch", "vcm_batch_create", "vcm_batch_run", "vcm_batch_get_info",
                  "vcm_batch_destroy", "vcm_server_create", "vcm_submit", "vcm_poll", "vcm_wait",
@@ -250,6 +264,7 @@ def make_query(q: scenes.Query, precision: int = VCM_FP32_RECHECK) -> vcm_query:
     P.mode, P.theta_blocks = int(p.mode), int(p.theta_blocks)
     P.recheck_eps = float(p.recheck_eps)
     P.precision = int(precision)
+    P.gaze = int(getattr(p, "gaze", 0))
     return Q
 
 
@@ -309,7 +324,8 @@ def vcm_index_get_info(index: Index) -> Dict[str, float]:
     _check(load_library().vcm_index_get_info(index.handle, ctypes.byref(info)))
     return {"n_boxes": info.n_boxes, "n_refs": info.n_refs, "nx": info.nx, "ny": info.ny,
             "cell_size": info.cell_size, "origin": (info.origin[0], info.origin[1]),
-            "device_bytes": info.device_bytes, "build_ms": info.build_ms}
+            "device_bytes": info.device_bytes, "build_ms": info.build_ms,
+            "kernel_ms": info.kernel_ms, "longest_list": info.longest_list}
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -493,6 +509,42 @@ class Server:
             _check(load_library().vcm_server_destroy(self.handle))
             self.handle = ctypes.c_void_p()
             self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class View:
+    """Incremental processing (vcm_view_*): the query's visibility kept at a
+    360-degree field of view; render() colours it for any field of view and
+    gaze without tracing again."""
+
+    def __init__(self, index: Index, query: scenes.Query, stream=None, precision: int = VCM_FP32_RECHECK):
+        L = load_library()
+        self._index = index
+        self.query = query
+        Q = make_query(query, precision)
+        h = ctypes.c_void_p()
+        _check(L.vcm_view_create(index.handle, ctypes.byref(Q), _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def render(self, fov_deg: float, gaze: int, bin_out, c_out=None, count_out=None, stream=None):
+        R = _make_result(self.query.grid.count, bin_out, c_out, count_out)
+        _check(load_library().vcm_view_render(self.handle, float(fov_deg), int(gaze), ctypes.byref(R),
+                                              _stream_ptr(stream)))
+
+    def info(self):
+        i = vcm_view_info()
+        _check(load_library().vcm_view_get_info(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in vcm_view_info._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(load_library().vcm_view_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -12,7 +12,7 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.hip", "index.hip", "brute.hip", "blocks.hip", "pruned.hip", "error.hip", "batch.hip", "serve.hip",
-           "tune.hip"]
+           "tune.hip", "view.hip"]
 
 # Packed float32 instructions are disabled for every HIP translation unit.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

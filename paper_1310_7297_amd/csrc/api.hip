@@ -152,8 +152,9 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
     if (!(P.mu_arcmin > 0)) return set_error(VCM_E_INVALID, "mu_arcmin must be > 0");
     if (!(P.near_d0 > 0)) return set_error(VCM_E_INVALID, "near_d0 must be > 0");
     if (!(P.fov_deg > 0 && P.fov_deg <= 360)) return set_error(VCM_E_INVALID, "fov_deg must be in (0, 360]");
-    if (T.kind == VCM_CUBE && P.fov_deg < 360)
-        return set_error(VCM_E_INVALID, "a cube has no normal: use fov_deg = 360");
+    if (P.gaze < -dim || P.gaze > dim) return set_error(VCM_E_INVALID, "gaze must be 0 or +-(1 + axis), axis < dim");
+    if (T.kind == VCM_CUBE && P.fov_deg < 360 && P.gaze == 0)
+        return set_error(VCM_E_INVALID, "a cube has no normal: give a gaze, or use fov_deg = 360");
     if (P.n_bins < 2 || P.n_bins > 256) return set_error(VCM_E_INVALID, "n_bins must be in [2, 256]");
     if (P.bin_scale != VCM_BIN_LINEAR && P.bin_scale != VCM_BIN_LOG)
         return set_error(VCM_E_INVALID, "unknown bin_scale");
@@ -202,6 +203,8 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
     g->count = count;
 
     *p = ParamDesc{};
+    p->fov_axis = P.gaze == 0 ? T.normal_axis : std::abs(P.gaze) - 1;
+    p->fov_sign = P.gaze == 0 ? T.normal_sign : (P.gaze > 0 ? 1 : -1);
     const double half_fov = P.fov_deg / 2.0;
     if (half_fov >= 180.0) {
         p->fov_kind = kFovAll;
@@ -290,7 +293,7 @@ vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, co
     for (int l = 1; l <= w.plan.levels; ++l) lists[l] = reinterpret_cast<uint32_t *>(ws + w.lists[l]);
     unsigned *ctr = reinterpret_cast<unsigned *>(ws + w.ctr);
     vcm_status st = launch_blocks(ix, t, g, p, w.plan, gate, lists, ctr, s, stats);
-    const int lv = block_classified_levels(w.plan);
+    const int lv = w.plan.leaf_list;
     if (st == VCM_OK)
         st = launch_leaves(ix, t, g, p, w.plan, gate, lists[lv], ctr + lv, ctr + 2 * w.plan.levels + 1, s, stats);
     if (st == VCM_OK)
@@ -411,6 +414,8 @@ vcm_status vcm_index_get_info(const vcm_index *index, vcm_index_info *info) {
     info->origin[1] = ix.frame[1];
     info->device_bytes = ix.bytes;
     info->build_ms = ix.build_ms;
+    info->kernel_ms = ix.build_kernel_ms;
+    info->longest_list = ix.longest_list;
     return VCM_OK;
 }
 

@@ -66,6 +66,40 @@ __device__ inline bool hull_meets(const float *L, const float *H, const float *s
     return ok && ln * ud <= un * ld;
 }
 
+// Exact: does the closed box [a, c] meet the convex hull of the boxes [L, H]
+// and [F0, F1]?  That hull is the union over lambda in [0, 1] of the boxes
+// [L + lambda (F0 - L), H + lambda (F1 - H)]; per axis, two linear
+// constraints on lambda, as in hull_meets.
+template <int DIM>
+__device__ inline bool hull2_meets(const float *L, const float *H, const float *F0, const float *F1,
+                                   const float *a, const float *c) {
+    double ln = 0.0, ld = 1.0, un = 1.0, ud = 1.0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            // side 0: L + l (F0 - L) <= c;  side 1: H + l (F1 - H) >= a,
+            // both written l x <= y
+            const double x = side ? double(H[k] - F1[k]) : double(F0[k] - L[k]);
+            const double y = side ? double(H[k] - a[k]) : double(c[k] - L[k]);
+            if (x > 0.0) {
+                if (y * ud < un * x) {
+                    un = y;
+                    ud = x;
+                }
+            } else if (x < 0.0) {
+                if (-y * ld > ln * -x) {
+                    ln = -y;
+                    ld = -x;
+                }
+            } else {
+                ok = ok && y >= 0.0;
+            }
+        }
+    return ok && ln * ud <= un * ld;
+}
+
 struct BlockLevel {
     DevIndex idx;
     TargetDesc tgt;
@@ -75,14 +109,15 @@ struct BlockLevel {
     const uint32_t *in_list;   // blocks of this level (index in its block grid); null: all
     const uint32_t *in_count;  // entries of in_list
     uint32_t n_all;            // blocks of this level when in_list is null
-    uint32_t *out_list;        // octants of undecided blocks, or (last level) the blocks
+    uint32_t *out_list;        // sub-blocks of undecided blocks, or the blocks themselves
     uint32_t *out_count;
     unsigned *claim;           // work counter of this launch
     DevStats *stats;
     int32_t side;              // viewpoints per block edge
     int32_t nb[3];             // blocks per axis at this level
-    int32_t nbc[3];            // blocks per axis one level down (side / 2)
-    int32_t last;              // smallest blocks: undecided ones are listed unsplit
+    int32_t child;             // edge of the sub-blocks listed for undecided blocks;
+                               // 0: list the undecided blocks themselves
+    int32_t nbc[3];            // sub-blocks per axis over the grid
 };
 
 // Position of viewpoint index i along axis k (exact).
@@ -149,8 +184,10 @@ __device__ inline void block_walk(const BlockLevel &B, cptr_i32 col_start, cptr_
                 // lists are sorted by decreasing top and end with a sentinel
                 // whose top is -inf: the scan ends below the hull's floor
                 const bool above = R.hi[2] >= zf;
-                const bool cand = above && R.id >= 0 && R.hi[BX] >= bl && R.lo[BX] <= bh &&
-                                  (DIM == 2 || R.lo[2] <= zc);
+                bool cand = above && R.id >= 0 && R.hi[BX] >= bl && R.lo[BX] <= bh && (DIM == 2 || R.lo[2] <= zc);
+                // exactly: only a box that meets the hull of the block and the
+                // target's box can meet a line of sight from the block
+                if (cand) cand = hull2_meets<DIM>(L, H, F0, F1, R.lo, R.hi);
                 unsigned long long cm = __ballot(cand);
                 const unsigned long long below = __ballot(!above);
                 while (cm) {
@@ -204,7 +241,7 @@ __device__ inline int fov_class(const TargetDesc &T, const ParamDesc &P, const f
 #pragma unroll
         for (int k = 0; k < 3; ++k) q[k] = ((c >> k) & 1) ? H[k] : L[k];
         const bool in = in_wedge<DIM>(T, P, q);
-        const double dn = T.nsign * (double(q[T.nax]) - double(T.c[T.nax]));
+        const double dn = P.fov_sign * (double(q[P.fov_axis]) - double(T.c[P.fov_axis]));
         all_in = all_in && in;
         all_out = all_out && !in;
         all_front = all_front && dn >= 0.0;
@@ -380,32 +417,30 @@ __global__ __launch_bounds__(256) void k_blocks(BlockLevel B, const int32_t *col
                 const int i = lo[0] + t % e0, j = lo[1] + (t / e0) % e1, k = lo[2] + t / (e0 * e1);
                 B.gate[i + static_cast<int64_t>(G.n[0]) * (j + static_cast<int64_t>(G.n[1]) * k)] = word;
             }
-        } else if (B.last) {
+        } else if (B.child == 0) {
             if (lane == 0) B.out_list[atomicAdd(B.out_count, 1u)] = b;
         } else {
-            // octants that hold viewpoints, one level down
-            const int half = B.side / 2;
-            int nch = 0;
-            uint32_t mine = 0;
-            for (int o = 0; o < 8; ++o) {
-                int c[3];
-                bool in = true;
+            // the sub-blocks of edge B.child that hold viewpoints (at most 64:
+            // the octants, or the viewpoints of a block of edge 4), lane t
+            // taking sub-block t
+            const int r = B.side / B.child;
+            const int tot = DIM == 3 ? r * r * r : r * r;
+            int c[3] = {0, 0, 0};
+            bool in = lane < tot;
+            c[0] = bi[0] * r + lane % r;
+            c[1] = bi[1] * r + (lane / r) % r;
+            c[2] = DIM == 3 ? bi[2] * r + lane / (r * r) : 0;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    c[k] = 2 * bi[k] + ((o >> k) & 1);
-                    in = in && (k < DIM ? c[k] * half < G.n[k] : c[k] == 0);
-                }
-                if (!in) continue;
-                const uint32_t id = static_cast<uint32_t>(c[0]) +
-                                    static_cast<uint32_t>(B.nbc[0]) *
-                                        (static_cast<uint32_t>(c[1]) + static_cast<uint32_t>(B.nbc[1]) * c[2]);
-                if (lane == nch) mine = id;
-                ++nch;
-            }
+            for (int k = 0; k < DIM; ++k) in = in && c[k] * B.child < G.n[k];
+            const unsigned long long mask = __ballot(in);
             uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(B.out_count, static_cast<uint32_t>(nch));
+            if (lane == 0 && mask) base = atomicAdd(B.out_count, static_cast<uint32_t>(__popcll(mask)));
             base = __shfl(base, 0);
-            if (lane < nch) B.out_list[base + lane] = mine;
+            if (in)
+                B.out_list[base + mbcnt(mask)] =
+                    static_cast<uint32_t>(c[0]) +
+                    static_cast<uint32_t>(B.nbc[0]) *
+                        (static_cast<uint32_t>(c[1]) + static_cast<uint32_t>(B.nbc[1]) * static_cast<uint32_t>(c[2]));
         }
     }
     if (B.stats && lane == 0) {
@@ -429,7 +464,9 @@ void dispatch_blocks(int ns, F &&f) {
 
 }  // namespace
 
-int block_classified_levels(const BlockPlan &bp) { return bp.leaf == 1 ? bp.levels - 1 : bp.levels; }
+// An undecided block hands down at most 64 sub-blocks, one per lane.
+static_assert(kMinClassifiedSide >= 2 && kMinClassifiedSide <= 4, "sub-blocks of a block must fit one wavefront");
+static_assert(kRootBlockSide >= kMinClassifiedSide, "the root level is classified");
 
 int block_leaf_side(int theta) {
     int s = 1;
@@ -447,8 +484,13 @@ BlockPlan block_plan(const GridDesc &g, int dim, int theta) {
         for (int k = 0; k < 3; ++k) n *= k < dim ? (g.n[k] + s - 1) / s : 1;
         bp.side[bp.levels] = s;
         bp.count[bp.levels] = n;
+        if (bp.leaf > 1 || s >= kMinClassifiedSide) bp.classified = bp.levels + 1;
         ++bp.levels;
     }
+    if (bp.classified == 0) bp.classified = 1;
+    // the ray kernel's list: the undecided smallest blocks; with theta = 1,
+    // the viewpoints of the undecided blocks of the last classified level
+    bp.leaf_list = bp.leaf > 1 ? bp.levels : bp.levels - 1;
     return bp;
 }
 
@@ -461,10 +503,7 @@ vcm_status launch_blocks(const Index &ix, const TargetDesc &t, const GridDesc &g
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, ctr, nctr);
     const int cus = device_cus(ix.device);
     const int ns = slots_for(t);
-    // single viewpoints are not classified: the ray kernel traces them (a
-    // one-viewpoint block is always decidable, but tracing is cheaper)
-    const int classified = block_classified_levels(bp);
-    for (int l = 0; l < classified; ++l) {
+    for (int l = 0; l < bp.classified; ++l) {
         BlockLevel B{};
         B.idx = ix.dev;
         B.tgt = t;
@@ -474,16 +513,20 @@ vcm_status launch_blocks(const Index &ix, const TargetDesc &t, const GridDesc &g
         B.in_list = l == 0 ? nullptr : lists[l];
         B.in_count = l == 0 ? nullptr : ctr + l;
         B.n_all = static_cast<uint32_t>(bp.count[0]);
-        B.out_list = lists[l + 1];
-        B.out_count = ctr + l + 1;
+        const bool last = l == bp.classified - 1;
+        B.out_list = last ? lists[bp.leaf_list] : lists[l + 1];
+        B.out_count = last ? ctr + bp.leaf_list : ctr + l + 1;
         B.claim = ctr + bp.levels + 1 + l;
         B.stats = stats;
         B.side = bp.side[l];
-        B.last = l == bp.levels - 1;
-        const int half = std::max(1, bp.side[l] / 2);
+        // sub-blocks of undecided blocks: the next level's; at the last
+        // classified level, none (theta > 1: the block is a smallest block)
+        // or its viewpoints (theta = 1)
+        B.child = !last ? bp.side[l] / 2 : (bp.leaf > 1 ? 0 : 1);
+        const int cs = std::max(1, B.child);
         for (int k = 0; k < 3; ++k) {
             B.nb[k] = k < ix.dim ? (g.n[k] + B.side - 1) / B.side : 1;
-            B.nbc[k] = k < ix.dim ? (g.n[k] + half - 1) / half : 1;
+            B.nbc[k] = k < ix.dim ? (g.n[k] + cs - 1) / cs : 1;
         }
         const int64_t want = l == 0 ? (bp.count[0] + 3) / 4 : int64_t(cus) * 8;
         const dim3 grid(static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(cus) * 8))));

@@ -548,17 +548,9 @@ __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &
                 const int ik = k == 0 ? x0 + lane : (k == 1 ? jj : kk);
                 q[k] = (k < DIM) ? A.grid.o[k] + static_cast<float>(2 * ik + 1) * A.grid.h2[k] : 0.0f;
             }
-            R col = R(0);
-            if (o_cnt > 0) {
-                col = raw_colour<DIM, R>(T, P, q);
-                if (MODE == VCM_FRACTION) col = (R(o_cnt) / R(o_n)) * col;
-            }
-            R cb = col;
-            if (P.bin_scale == VCM_BIN_LOG) {
-                const R veff = col * R(P.V0);
-                cb = veff <= R(P.mu) ? R(0) : fmin(R(1), log(veff / R(P.mu)) * R(P.inv_log_V0_mu));
-            }
-            const int bn = min(P.n_bins - 1, static_cast<int>(floor(cb * R(P.n_bins))));
+            R col;
+            int bn;
+            colour_and_bin<DIM, R, MODE>(T, P, q, o_cnt, o_n, col, bn);
             A.bin[v0 + lane] = static_cast<uint8_t>(bn);
             if (A.c) A.c[v0 + lane] = static_cast<float>(col);
             if (A.count) A.count[v0 + lane] = static_cast<uint16_t>(o_cnt);
@@ -674,6 +666,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE
 // takes the gate of its representative viewpoint -- the lowest-index centre
 // viewpoint of the block -- traced like any viewpoint, for all the
 // viewpoints it holds.  One wavefront per block.
+constexpr int kLeafRun = 8;
+
 struct LeafArgs {
     const uint32_t *list;   // blocks (index in the leaf level's block grid)
     const unsigned *count;  // entries of list
@@ -698,12 +692,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE
     WaveStats ws;
     unsigned long long n_disagree = 0, n_leaves = 0;
     const unsigned n_in = *LA.count;
+    // A wavefront claims a run of kLeafRun consecutive entries: the octants
+    // an undecided block hands down sit next to each other in the list, so
+    // the box that blocked one leaf (FULL mode) is tried first on the next.
+    int blk = -1;
+    unsigned item = 0, end = 0;
     for (;;) {
-        unsigned item = 0;
-        if (lane == 0) item = atomicAdd(LA.claim, 1u);
-        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
-        if (item >= n_in) break;
-        const uint32_t b = LA.list[item];
+        if (item >= end) {
+            unsigned first = 0;
+            if (lane == 0) first = atomicAdd(LA.claim, static_cast<unsigned>(kLeafRun));
+            first = __builtin_amdgcn_readfirstlane(__shfl(first, 0));
+            if (first >= n_in) break;
+            item = first;
+            end = min(n_in, first + static_cast<unsigned>(kLeafRun));
+        }
+        const uint32_t b = LA.list[item++];
         const int bi[3] = {static_cast<int>(b % static_cast<uint32_t>(LA.nb[0])),
                            static_cast<int>((b / static_cast<uint32_t>(LA.nb[0])) % static_cast<uint32_t>(LA.nb[1])),
                            static_cast<int>(b / (static_cast<uint32_t>(LA.nb[0]) * static_cast<uint32_t>(LA.nb[1])))};
@@ -736,7 +739,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE
         int cnt = 0;
         if (fov && N > 0) {
             if (STATS) ws.rays += N;
-            int blk = -1;
             const int vis = trace_viewpoint<DIM, NS, EXACT64, MODE, STATS, kTabBlock>(
                 A, col_start, recs, q, faces, N, lds, s_tab, blk, ws, n_disagree);
             cnt = MODE == VCM_FRACTION ? vis : (vis == N ? N : 0);

@@ -44,35 +44,87 @@ __global__ void k_count(const float *__restrict__ lo, const float *__restrict__ 
 }
 
 // Exclusive scan of the list lengths (count + 1 for the sentinel that ends
-// every column) into out[0..n], by one workgroup of 1024.
-__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ counts, int32_t n,
-                                               int32_t *__restrict__ out) {
-    __shared__ int32_t part[1024];
-    const int32_t t = threadIdx.x;
-    const int32_t chunk = (n + 1023) / 1024;
-    const int32_t b = min(n, t * chunk), e = min(n, b + chunk);
-    int32_t s = 0;
-    for (int32_t i = b; i < e; ++i) s += counts[i] + 1;
-    part[t] = s;
+// every column) into out[0..n], in three passes so that any number of columns
+// spreads over the chip: each workgroup scans a tile of kScanTile columns and
+// leaves the tile's total; one workgroup scans the totals; every tile then
+// adds its offset.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+// Exclusive scan of one value per thread across a workgroup of kScanThreads;
+// returns the workgroup's total.
+__device__ inline int32_t block_exclusive_scan(int32_t &v, int32_t *part) {
+    const int t = threadIdx.x;
+    part[t] = v;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums.
-    for (int32_t off = 1; off < 1024; off <<= 1) {
-        int32_t v = (t >= off) ? part[t - off] : 0;
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int32_t a = t >= off ? part[t - off] : 0;
         __syncthreads();
-        part[t] += v;
+        part[t] += a;
         __syncthreads();
     }
-    int32_t run = part[t] - s;
-    for (int32_t i = b; i < e; ++i) {
-        out[i] = run;
-        run += counts[i] + 1;
+    const int32_t total = part[kScanThreads - 1];
+    v = part[t] - v;
+    __syncthreads();
+    return total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int32_t *__restrict__ counts, int32_t n,
+                                                             int32_t *__restrict__ out,
+                                                             int32_t *__restrict__ tile_sums) {
+    __shared__ int32_t part[kScanThreads];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanPer;
+    int32_t v[kScanPer], s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = base + k < n ? counts[base + k] + 1 : 0;
+        s += v[k];
     }
-    if (t == 1023) out[n] = part[1023];
+    const int32_t total = block_exclusive_scan(s, part);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < n) out[base + k] = s;
+        s += v[k];
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the tile totals in place, the grand total
+// into out[n].
+__global__ __launch_bounds__(kScanThreads) void k_scan_totals(int32_t *__restrict__ tile_sums, int32_t tiles,
+                                                              int32_t *__restrict__ out, int32_t n) {
+    __shared__ int32_t part[kScanThreads];
+    int32_t carry = 0;
+    for (int32_t b = 0; b < tiles; b += kScanThreads) {
+        const int32_t i = b + threadIdx.x;
+        int32_t v = i < tiles ? tile_sums[i] : 0;
+        const int32_t total = block_exclusive_scan(v, part);
+        if (i < tiles) tile_sums[i] = v + carry;
+        carry += total;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(const int32_t *__restrict__ tile_sums, int32_t n,
+                                                           int32_t *__restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x;
+    const int32_t add = tile_sums[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+        if (i + k * kScanThreads < n) out[i + k * kScanThreads] += add;
+}
+
+// Sort key of a record: decreasing top height, then increasing box id.  Tops
+// are >= 0 in the index frame (or +inf), so their bit patterns order as
+// unsigned integers.
+__device__ inline uint64_t sort_key(float top, int32_t id) {
+    return (static_cast<uint64_t>(~__float_as_uint(top)) << 32) | static_cast<uint32_t>(id);
 }
 
 __global__ void k_fill(const float *__restrict__ lo, const float *__restrict__ hi, int64_t n,
                        int32_t dim, BuildGrid g, int32_t *__restrict__ cursor,
-                       BoxRec *__restrict__ recs) {
+                       BoxRec *__restrict__ recs, uint64_t *__restrict__ keys) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     BoxRec r;
@@ -84,6 +136,7 @@ __global__ void k_fill(const float *__restrict__ lo, const float *__restrict__ h
     }
     r.id = static_cast<int32_t>(i);
     r.pad = 0;
+    const uint64_t key = sort_key(r.hi[2], r.id);
     int32_t ax, bx, ay, by;
     footprint_cols(r.lo[0], r.hi[0], 0.0f, g.inv_cs, g.nx, ax, bx);
     footprint_cols(r.lo[1], r.hi[1], 0.0f, g.inv_cs, g.ny, ay, by);
@@ -91,40 +144,50 @@ __global__ void k_fill(const float *__restrict__ lo, const float *__restrict__ h
         for (int32_t x = ax; x <= bx; ++x) {
             int32_t slot = atomicAdd(&cursor[y * g.nx + x], 1);
             recs[slot] = r;
+            keys[slot] = key;
         }
 }
 
-// Sort each column list by (top height descending, box id ascending), which
-// also makes the index independent of the order the atomics handed out slots,
-// and end it with the sentinel: a record whose top is -inf, bit pattern
-// 0xff800000, so that its difference with any floor of the traversal (an
-// ordered integer in [0, 0x7f800000]) is negative as a signed integer, and
-// whose lower corner is +inf.
-__global__ void k_sort(const int32_t *__restrict__ col_start, int32_t ncols,
-                       BoxRec *__restrict__ recs) {
-    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncols) return;
-    const int32_t b = col_start[c], e = col_start[c + 1] - 1;
-    BoxRec sen;
-    for (int k = 0; k < 3; ++k) {
-        sen.lo[k] = INFINITY;
-        sen.hi[k] = -INFINITY;
+// Sort every column list by (top height descending, box id ascending), which
+// also makes the index independent of the order the atomics handed out
+// slots, and end it with the sentinel: a record whose top is -inf, bit
+// pattern 0xff800000, so that its difference with any floor of the traversal
+// (an ordered integer in [0, 0x7f800000]) is negative as a signed integer,
+// and whose lower corner is +inf.
+//
+// One thread per slot of the filled lists: it finds its column by binary
+// search over the list starts and moves its record to the rank of its key
+// among the column's keys (keys are distinct, so the ranks are a
+// permutation).  A column of n records costs n key reads per record, all
+// columns in parallel; neighbouring threads of one column read the same key
+// at the same time.
+__global__ __launch_bounds__(256) void k_rank(const int32_t *__restrict__ col_start, int32_t ncols,
+                                              const BoxRec *__restrict__ in, const uint64_t *__restrict__ keys,
+                                              int32_t total, BoxRec *__restrict__ out) {
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= total) return;
+    int32_t a = 0, b = ncols;  // col_start[a] <= p < col_start[b]
+    while (b - a > 1) {
+        const int32_t m = (a + b) >> 1;
+        if (col_start[m] <= p) a = m;
+        else b = m;
     }
-    sen.id = -1;
-    sen.pad = 0;
-    recs[e] = sen;
-    for (int32_t i = b + 1; i < e; ++i) {
-        BoxRec key = recs[i];
-        int32_t j = i - 1;
-        while (j >= b) {
-            const BoxRec &o = recs[j];
-            bool after = (o.hi[2] < key.hi[2]) || (o.hi[2] == key.hi[2] && o.id > key.id);
-            if (!after) break;
-            recs[j + 1] = o;
-            --j;
+    const int32_t cb = col_start[a], ce = col_start[a + 1] - 1;  // ce: the sentinel's slot
+    if (p == ce) {
+        BoxRec sen;
+        for (int k = 0; k < 3; ++k) {
+            sen.lo[k] = INFINITY;
+            sen.hi[k] = -INFINITY;
         }
-        recs[j + 1] = key;
+        sen.id = -1;
+        sen.pad = 0;
+        out[p] = sen;
+        return;
     }
+    const uint64_t key = keys[p];
+    int32_t rank = 0;
+    for (int32_t j = cb; j < ce; ++j) rank += keys[j] < key;
+    out[cb + rank] = in[p];
 }
 
 #define HIP_TRY(expr)                                                                       \
@@ -180,49 +243,90 @@ vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, i
     BuildGrid g{(float)x0, (float)y0, (float)mnz, (float)(1.0 / cs), (int32_t)nx, (int32_t)ny};
 
     float *d_lo = nullptr, *d_hi = nullptr;
-    int32_t *d_counts = nullptr, *d_cursor = nullptr;
+    int32_t *d_counts = nullptr, *d_cursor = nullptr, *d_tiles = nullptr;
+    BoxRec *d_tmp = nullptr;
+    uint64_t *d_keys = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // every exit frees what the build allocated for itself
+    struct Cleanup {
+        float *&lo, *&hi;
+        int32_t *&counts, *&cursor, *&tiles;
+        BoxRec *&tmp;
+        uint64_t *&keys;
+        hipEvent_t *ev;
+        ~Cleanup() {
+            if (lo) hipFree(lo);
+            if (hi) hipFree(hi);
+            if (counts) hipFree(counts);
+            if (cursor) hipFree(cursor);
+            if (tiles) hipFree(tiles);
+            if (tmp) hipFree(tmp);
+            if (keys) hipFree(keys);
+            for (int k = 0; k < 4; ++k)
+                if (ev[k]) hipEventDestroy(ev[k]);
+        }
+    } cleanup{d_lo, d_hi, d_counts, d_cursor, d_tiles, d_tmp, d_keys, ev};
     const size_t nb = (size_t)std::max<int64_t>(n, 1) * 3 * sizeof(float);
+    const int32_t tiles = (ncols + kScanTile - 1) / kScanTile;
     HIP_TRY(hipMalloc(&d_lo, nb));
     HIP_TRY(hipMalloc(&d_hi, nb));
     HIP_TRY(hipMalloc(&d_counts, sizeof(int32_t) * ncols));
+    HIP_TRY(hipMalloc(&d_tiles, sizeof(int32_t) * tiles));
     HIP_TRY(hipMalloc(&ix->d_col_start, sizeof(int32_t) * (ncols + 1)));
     HIP_TRY(hipMalloc(&d_cursor, sizeof(int32_t) * ncols));
+    for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&ev[k]));
     if (n > 0) {
         HIP_TRY(hipMemcpyAsync(d_lo, h_lo, sizeof(float) * 3 * n, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipMemcpyAsync(d_hi, h_hi, sizeof(float) * 3 * n, hipMemcpyHostToDevice, stream));
     }
     HIP_TRY(hipMemsetAsync(d_counts, 0, sizeof(int32_t) * ncols, stream));
+    HIP_TRY(hipEventRecord(ev[0], stream));
     const int T = 256;
     if (n > 0)
         hipLaunchKernelGGL(k_count, dim3((unsigned)((n + T - 1) / T)), dim3(T), 0, stream, d_lo,
                            d_hi, n, g, d_counts);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, d_counts, ncols, ix->d_col_start);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanThreads), 0, stream, d_counts, ncols,
+                       ix->d_col_start, d_tiles);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, stream, d_tiles, tiles,
+                       ix->d_col_start, ncols);
+    hipLaunchKernelGGL(k_scan_add, dim3(tiles), dim3(kScanThreads), 0, stream, d_tiles, ncols,
+                       ix->d_col_start);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(ev[1], stream));
     int32_t total = 0;
     HIP_TRY(hipMemcpyAsync(&total, ix->d_col_start + ncols, sizeof(int32_t),
                            hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     HIP_TRY(hipMalloc(&ix->d_recs, sizeof(BoxRec) * std::max(total, 1)));
+    HIP_TRY(hipMalloc(&d_tmp, sizeof(BoxRec) * std::max(total, 1)));
+    HIP_TRY(hipMalloc(&d_keys, sizeof(uint64_t) * std::max(total, 1)));
     BoxRec *d_recs = ix->d_recs;
+    HIP_TRY(hipEventRecord(ev[2], stream));
     HIP_TRY(hipMemcpyAsync(d_cursor, ix->d_col_start, sizeof(int32_t) * ncols,
                            hipMemcpyDeviceToDevice, stream));
     if (n > 0)
         hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + T - 1) / T)), dim3(T), 0, stream, d_lo,
-                           d_hi, n, ix->dim, g, d_cursor, d_recs);
-    hipLaunchKernelGGL(k_sort, dim3((unsigned)((ncols + T - 1) / T)), dim3(T), 0, stream,
-                       ix->d_col_start, ncols, d_recs);
+                           d_hi, n, ix->dim, g, d_cursor, d_tmp, d_keys);
+    hipLaunchKernelGGL(k_rank, dim3((unsigned)((total + T - 1) / T)), dim3(T), 0, stream,
+                       ix->d_col_start, ncols, d_tmp, d_keys, total, d_recs);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(ev[3], stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    // device time of the build kernels (the host's wait for the list total
+    // between the two halves is not counted)
+    float ms_a = 0.0f, ms_b = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms_a, ev[0], ev[1]));
+    HIP_TRY(hipEventElapsedTime(&ms_b, ev[2], ev[3]));
+    const double all_ms = static_cast<double>(ms_a) + ms_b;
     // host copy of the lists, for argument checks that need the obstacles
     ix->h_col_start.resize(static_cast<size_t>(ncols) + 1);
     ix->h_recs.resize(static_cast<size_t>(std::max(total, 1)));
     HIP_TRY(hipMemcpy(ix->h_col_start.data(), ix->d_col_start, sizeof(int32_t) * (ncols + 1),
                       hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(ix->h_recs.data(), d_recs, sizeof(BoxRec) * std::max(total, 1), hipMemcpyDeviceToHost));
-    hipFree(d_lo);
-    hipFree(d_hi);
-    hipFree(d_counts);
-    hipFree(d_cursor);
+    int32_t longest = 0;
+    for (int32_t c = 0; c < ncols; ++c)
+        longest = std::max(longest, ix->h_col_start[c + 1] - ix->h_col_start[c] - 1);
 
     ix->n_boxes = n;
     ix->n_refs = total - ncols;  // without the sentinels
@@ -239,6 +343,8 @@ vcm_status build_index_device(Index *ix, const float *h_lo, const float *h_hi, i
     ix->dev.ny = (int32_t)ny;
     ix->dev.dim = ix->dim;
     ix->bytes = sizeof(int32_t) * (ncols + 1) + sizeof(BoxRec) * std::max(total, 1);
+    ix->longest_list = longest;
+    ix->build_kernel_ms = all_ms;
     ix->build_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return VCM_OK;

@@ -117,7 +117,7 @@ __device__ inline bool in_wedge(const TargetDesc &T, const ParamDesc &P, const f
     for (int k = 0; k < DIM; ++k) {
         const double d = double(q[k]) - double(T.c[k]);
         d2 += d * d;
-        if (k == T.nax) dn = T.nsign * d;
+        if (k == P.fov_axis) dn = P.fov_sign * d;
     }
     if (P.fov_kind == kFovHalf) return dn >= 0.0;
     if (P.fov_kind == kFovNarrow) return dn >= 0.0 && dn * dn >= P.fov_c2 * d2;
@@ -131,6 +131,28 @@ __device__ inline bool in_fov(const TargetDesc &T, const ParamDesc &P, const flo
     return in_region<DIM>(T, q) && in_wedge<DIM>(T, P, q);
 }
 
+
+// Colour and bin of viewpoint q from its visible count cnt of n live samples
+// (0 outside the field of view): the visual angle of Eq. 1 / Eq. 2 over V0,
+// scaled by the visible fraction in FRACTION mode, then binned in the
+// query's scale.  The ray kernel and the incremental re-colouring share it,
+// so that both give the same bits.
+template <int DIM, typename R, int MODE>
+__device__ __attribute__((always_inline)) inline void colour_and_bin(const TargetDesc &T, const ParamDesc &P,
+                                                                     const float *q, int cnt, int n, R &col,
+                                                                     int &bin) {
+    col = R(0);
+    if (cnt > 0) {
+        col = raw_colour<DIM, R>(T, P, q);
+        if (MODE == VCM_FRACTION) col = (R(cnt) / R(n)) * col;
+    }
+    R cb = col;
+    if (P.bin_scale == VCM_BIN_LOG) {
+        const R veff = col * R(P.V0);
+        cb = veff <= R(P.mu) ? R(0) : fmin(R(1), log(veff / R(P.mu)) * R(P.inv_log_V0_mu));
+    }
+    bin = min(P.n_bins - 1, static_cast<int>(floor(cb * R(P.n_bins))));
+}
 
 __device__ inline float readlane_f(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));

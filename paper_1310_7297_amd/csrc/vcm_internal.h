@@ -84,6 +84,8 @@ enum FovKind : int32_t { kFovAll = 0, kFovHalf = 1, kFovNarrow = 2, kFovWide = 3
 
 struct ParamDesc {
     double fov_c2;      // cos^2 of the half angle (exact for the table's FOVs)
+    int32_t fov_axis;   // axis and orientation of the wedge
+    int32_t fov_sign;
     int32_t fov_kind;
     int32_t n_bins;
     int32_t bin_scale;
@@ -176,6 +178,8 @@ struct Index {
     double frame[3] = {0, 0, 0};  // world coordinates of the frame origin
     size_t bytes = 0;
     double build_ms = 0.0;
+    double build_kernel_ms = 0.0;   // device time of the build kernels
+    int32_t longest_list = 0;       // records in the longest column list
     // Host copy of the column lists (same layout as on the device), used to
     // reject targets that meet an obstacle.
     std::vector<int32_t> h_col_start;
@@ -228,19 +232,27 @@ vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, cons
 // Visible-region tree of the pruned methods (blocks.hip): blocks of `side`
 // viewpoints per edge, from the root side down to the leaf side (the
 // largest power of two not above theta), halved at every level.
-constexpr int kRootBlockSide = 8;
-constexpr int kMaxBlockLevels = 8;
+#ifndef VCM_ROOT_BLOCK_SIDE
+#define VCM_ROOT_BLOCK_SIDE 8
+#endif
+#ifndef VCM_MIN_CLASSIFIED_SIDE
+#define VCM_MIN_CLASSIFIED_SIDE 4
+#endif
+constexpr int kRootBlockSide = VCM_ROOT_BLOCK_SIDE;
+// With theta = 1 every viewpoint the tree leaves undecided is traced exactly,
+// so blocks below this side are not classified: tracing their viewpoints
+// costs less than classifying them (measured).
+constexpr int kMinClassifiedSide = VCM_MIN_CLASSIFIED_SIDE;
+constexpr int kMaxBlockLevels = 16;
 struct BlockPlan {
     int leaf = 1, root = 1, levels = 0;
     int side[kMaxBlockLevels] = {};
     int64_t count[kMaxBlockLevels] = {};  // blocks of the level over the grid
+    int classified = 0;  // levels the block kernel classifies (from the root)
+    int leaf_list = 0;   // lists[leaf_list]: the blocks the ray kernel traces
 };
 int block_leaf_side(int theta);
 BlockPlan block_plan(const GridDesc &g, int dim, int theta);
-// Levels the block kernel classifies: all, or all but the single-viewpoint
-// level, whose blocks go to the ray kernel unclassified.  The undecided
-// smallest blocks are then lists[block_classified_levels(bp)].
-int block_classified_levels(const BlockPlan &bp);
 // Classify the tree's blocks level by level.  gate: one word per viewpoint,
 // written for the viewpoints of decided blocks; lists[l] (l = 1..levels)
 // receive the blocks of level l (lists[levels]: the undecided smallest

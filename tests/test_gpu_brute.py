@@ -251,3 +251,122 @@ def test_host_result_buffers():
     with pytest.raises(ValueError):                  # mixed host and device buffers
         vcm.vcm_compute(idx, q, hb, torch.empty(n, dtype=torch.float32, device="cuda"))
     idx.free()
+
+
+@pytest.mark.parametrize("mode", [FULL, FRACTION])
+def test_gaze_directions_against_oracle(mode):
+    """A field of view about a gaze direction other than the target's normal
+    (a cube looked at from above, a billboard's wedge turned), against the
+    oracle over whole small maps."""
+    for t, fov, gaze in ((Target(CUBE, (64.0, 64.0, 4.0), (8.0, 0.0), samples_u=4, samples_v=4), 120.0, 3),
+                         (Target(CUBE, (64.0, 64.0, 4.0), (8.0, 0.0), samples_u=4, samples_v=4), 240.0, -1),
+                         (Target(BILLBOARD, (64.0, 64.0, 6.0), (8.0, 4.0), normal_axis=0, samples_u=8,
+                                 samples_v=4), 90.0, 2)):
+        scene = scenes.city(128.0, 40, seed=11, side=(4.0, 16.0), targets=[t], clearance=2.0)
+        q = Query(t, Grid((0.0, 0.0, 0.0), (128.0, 128.0, 32.0), (32, 32, 8)),
+                  Params(n_bins=16, mode=mode, fov_deg=fov, gaze=gaze, bin_scale=BIN_LOG))
+        o = oracle.vcm_eval(scene, q, nthreads=NT)
+        compare(_gpu_map(scene, q), o, 16, label=f"gaze {gaze} fov {fov}")
+        assert 0 < o["infov"].sum() < q.grid.count
+
+
+# ------------------------------------------------------ full-size parity --
+
+@pytest.mark.parametrize("mode", [FRACTION, FULL])
+def test_city4km_cube_benchmark_sample(mode):
+    """The benchmark's configuration: the 128 m index the autotuner picks for
+    this map, checked on the benchmark's own 16,384-viewpoint sample (of which
+    few see the target) and on 8,192 viewpoints within 120 m of the target."""
+    scene, q = scenes.city4km_cube()
+    q = _with(q, mode=mode)
+    g = _gpu_map(scene, q, cell_size=128.0, stats=True)
+    bench = scenes.viewpoint_sample(q.grid, 16384, 12345)
+    vp = np.unique(np.concatenate([bench, _near_target(q.grid, q.target, 120.0, 8192, 7)]))
+    o = oracle.vcm_eval(scene, q, vp, nthreads=NT)
+    r = compare(g, o, 16, idx=vp, label=f"city4km_cube 128 m mode {mode}")
+    assert (o["count"] > 0).sum() > 500 and r["n"] >= 16384 + 4096
+
+
+@pytest.mark.parametrize("mode", [FRACTION, FULL])
+def test_city2km_billboard_whole_map(mode):
+    """Every viewpoint of the 2 km billboard map against the oracle (all host
+    cores)."""
+    scene, q = scenes.city2km_billboard()
+    q = _with(q, mode=mode)
+    g = _gpu_map(scene, q)
+    o = oracle.vcm_eval(scene, q, nthreads=NT)
+    compare(g, o, 16, label=f"city2km_billboard whole map mode {mode}")
+    assert (o["count"] > 0).sum() > 500
+
+
+@pytest.mark.parametrize("kind", [BILLBOARD, CUBE])
+@pytest.mark.parametrize("mode", [FRACTION, FULL])
+def test_fp64_3d_against_oracle(kind, mode):
+    """The float64 variant of the 3-D kernels (every ray test exact, measure
+    in float64): whole small maps, and a window of the 2 km city."""
+    if kind == CUBE:
+        t = Target(CUBE, (64.0, 64.0, 4.0), (8.0, 0.0), samples_u=8, samples_v=8)
+    else:
+        t = Target(BILLBOARD, (64.0, 64.0, 6.0), (8.0, 4.0), normal_axis=1, samples_u=16, samples_v=8)
+    scene = scenes.city(128.0, 50, seed=17, side=(4.0, 16.0), targets=[t], clearance=2.0)
+    q = Query(t, Grid((0.0, 0.0, 0.0), (128.0, 128.0, 32.0), (32, 32, 8)),
+              Params(n_bins=16, mode=mode, bin_scale=BIN_LOG))
+    compare(_gpu_map(scene, q, precision=vcm.VCM_FP64), oracle.vcm_eval(scene, q, nthreads=NT), 16,
+            label=f"fp64 small {kind} {mode}")
+    scene2, q2 = scenes.city2km_billboard()
+    q2 = Query(q2.target, Grid((800.0, 800.0, 0.0), (400.0, 400.0, 150.0), (64, 64, 32)),
+               Params(n_bins=16, mode=mode, bin_scale=BIN_LOG))
+    g2 = _gpu_map(scene2, q2, precision=vcm.VCM_FP64)
+    vp = scenes.viewpoint_sample(q2.grid, 4096, 9)
+    compare(g2, oracle.vcm_eval(scene2, q2, vp, nthreads=NT), 16, idx=vp, label=f"fp64 city2km {mode}")
+
+
+@pytest.fixture(scope="module")
+def city8km():
+    scene, qs = scenes.city8km_serving(n_requests=24)
+    return scene, qs
+
+
+def test_city8km_serving_queries_sampled(city8km):
+    """The 100,000-box 8 km serving city, whose coordinates are the largest
+    (up to 8 km): a seeded sample of every map of six queries of each grid
+    size, the viewpoints near the target included, against the oracle."""
+    scene, qs = city8km
+    idx = vcm.vcm_build_index(scene, cell_size=64.0)
+    checked = 0
+    for i, q in enumerate(qs[:10]):
+        for mode in (FRACTION, FULL):
+            qq = _with(q, mode=mode)
+            g = vcm.compute_map(idx, qq)
+            vp = np.unique(np.concatenate([scenes.viewpoint_sample(qq.grid, 96, 100 + i),
+                                           _near_target(qq.grid, qq.target, 100.0, 64, 200 + i)]))
+            o = oracle.vcm_eval(scene, qq, vp, nthreads=NT)
+            compare(g, o, 16, idx=vp, label=f"city8km query {i} mode {mode}")
+            checked += (o["count"] > 0).sum()
+    idx.free()
+    assert checked > 100
+
+
+def test_recheck_everything_at_full_size(city8km):
+    """Every ray test settled exactly gives the same maps at full size (the
+    4 km cube map at the benchmark's 128 m index, and 8 km serving queries),
+    and no float32 decision outside the default margin disagrees with it."""
+    import torch
+    scene, q = scenes.city4km_cube()
+    q = _with(q, mode=FRACTION)
+    idx = vcm.vcm_build_index(scene, cell_size=128.0)
+    a = vcm.compute_map(idx, q, stats=True)
+    b = vcm.compute_map(idx, _with(q, recheck_eps=math.inf), stats=True)
+    assert np.array_equal(a["count"], b["count"]) and np.array_equal(a["bin"], b["bin"])
+    assert np.array_equal(a["c"], b["c"])
+    assert b["stats"]["fp32_disagree"] == 0 and b["stats"]["rechecks"] == b["stats"]["box_tests"]
+    idx.free()
+    scene8, qs = city8km
+    idx = vcm.vcm_build_index(scene8, cell_size=64.0)
+    for q in qs[:4]:
+        q = _with(q, mode=FRACTION)
+        a = vcm.compute_map(idx, q, stats=True)
+        b = vcm.compute_map(idx, _with(q, recheck_eps=math.inf), stats=True)
+        assert np.array_equal(a["count"], b["count"]) and np.array_equal(a["c"], b["c"])
+        assert b["stats"]["fp32_disagree"] == 0
+    idx.free()

@@ -151,3 +151,20 @@ def test_map_error_worked_case():
     assert a == pytest.approx((0.5 + 0.25 + 0.25) / 1.75, rel=1e-15)
     z = torch.zeros(5, device="cuda")
     assert vcm.vcm_map_error(z, ce.new_ones(5)) == (0.0, 0.0)
+
+
+@pytest.mark.parametrize("theta", [2, 4])
+@pytest.mark.parametrize("mode", [FULL, FRACTION])
+@pytest.mark.parametrize("fov", [120.0, 240.0])
+def test_blocks_across_the_field_of_view(theta, mode, fov):
+    """Blocks that straddle the wedge are not decided as a whole; against the
+    oracle over a whole ragged map."""
+    t = Target(BILLBOARD, (64.0, 64.0, 6.0), (8.0, 4.0), normal_axis=1, normal_sign=-1, samples_u=8, samples_v=4)
+    scene = scenes.city(128.0, 40, seed=11, side=(4.0, 16.0), targets=[t], clearance=2.0)
+    g = Grid((0.0, 0.0, 0.0), (120.0, 116.0, 28.0), (30, 29, 7))
+    q = Query(t, g, Params(n_bins=16, method=1, mode=mode, fov_deg=fov, bin_scale=BIN_LOG, theta_blocks=theta))
+    gm = _gpu_map(scene, q)
+    vp = np.arange(g.count, dtype=np.int64)
+    o = oracle.vcm_eval_pruned(scene, q, 1, theta, vp, nthreads=8)
+    compare_pruned(gm, o, scene, q, vp, 1)
+    assert (o["count"] > 0).sum() > 50
