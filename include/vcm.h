@@ -263,7 +263,9 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query,
  * static device array of 64 MiB, one per device, held from the first call
  * on that device until the process ends.  A query that needs more scratch
  * than that fails with VCM_E_INVALID before any device work: a brute-force
- * map needs 2 KiB, a pruned map 4 bytes per theta-block more.  Every call on
+ * map needs 2 KiB, a pruned map about 4 bytes per viewpoint more (a gate
+ * word per viewpoint and the block lists of every level of the hierarchy),
+ * so grids of up to about 16 million viewpoints.  Every call on
  * one device shares the array, so calls that overlap on a device (other
  * streams, other threads) race; the caller must order them.  Enqueues on
  * `stream` and returns; results as for vcm_compute. */
@@ -354,7 +356,8 @@ vcm_status vcm_tune_cell_size(const vcm_obstacles *obstacles, const vcm_query *q
 /* A server keeps an index resident and serves VCM queries submitted from any
  * thread.  Admission is by device memory: a request's footprint is its result
  * buffers (1 B bin + 4 B colour + 2 B count per viewpoint, for the buffers
- * given), its work record and, for the pruned methods, 4 B per theta-block;
+ * given), its work record and, for the pruned methods, the workspace of the
+ * block hierarchy (4 B per viewpoint and 4 B per block of every level);
  * a request is admitted while the footprints of all unfinished requests fit
  * in mem_budget_bytes.  One engine thread batches the admitted requests as
  * they arrive: whenever one of max_inflight launch slots (streams) is free it
@@ -404,8 +407,14 @@ vcm_status vcm_poll(vcm_server *server, uint64_t ticket, vcm_request_info *info)
 /* vcm_poll after waiting up to timeout_ms (< 0: no limit) for the request. */
 vcm_status vcm_wait(vcm_server *server, uint64_t ticket, int32_t timeout_ms,
                     vcm_request_info *info);
-/* Wait until every admitted request has finished. */
+/* Wait until every admitted request has finished (while launches are held,
+ * until every launch in flight has finished). */
 vcm_status vcm_server_drain(vcm_server *server);
+/* hold != 0: admitted requests queue but no launch starts; hold == 0:
+ * release, and every free launch slot takes up to max_batch of the queued
+ * requests at once.  For callers that gather a burst into as few launches as
+ * possible, and for tests of batching that must not depend on timing. */
+vcm_status vcm_server_hold(vcm_server *server, int32_t hold);
 vcm_status vcm_server_get_stats(vcm_server *server, vcm_server_stats *stats);
 vcm_status vcm_server_reset_stats(vcm_server *server);
 /* Stop the engine: requests not yet launched finish with VCM_E_INTERNAL

@@ -30,8 +30,8 @@ EXPORTS = ("vcm_last_error", "vcm_version", "vcm_build_index", "vcm_free_index",
            "vcm_index_get_info", "vcm_compute", "vcm_compute_noalloc", "vcm_compute_batch",
            "vcm_batch_create",
            "vcm_batch_run", "vcm_batch_get_info", "vcm_batch_destroy", "vcm_server_create",
-           "vcm_submit", "vcm_poll", "vcm_wait", "vcm_server_drain", "vcm_server_get_stats",
-           "vcm_server_reset_stats", "vcm_server_destroy", "vcm_tune_cell_size", "vcm_map_error",
+           "vcm_submit", "vcm_poll", "vcm_wait", "vcm_server_drain", "vcm_server_hold",
+           "vcm_server_get_stats", "vcm_server_reset_stats", "vcm_server_destroy", "vcm_tune_cell_size", "vcm_map_error",
            "vcm_error_bounds", "vcm_view_create", "vcm_view_render", "vcm_view_get_info",
            "vcm_view_destroy")
 
@@ -213,12 +213,13 @@ def load_library(path: Optional[str] = None):
                                   ctypes.POINTER(vcm_result), ctypes.c_void_p]
     L.vcm_view_get_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(vcm_view_info)]
     L.vcm_view_destroy.argtypes = [ctypes.c_void_p]
+    L.vcm_server_hold.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     for name in ("vcm_view_create", "vcm_view_render", "vcm_view_get_info", "vcm_view_destroy",
                  "vcm_build_index", "vcm_free_index", "vcm_index_get_info", "vcm_compute",
                  "vcm_compute_noalloc",
                  "vcm_compute_batch", "vcm_batch_create", "vcm_batch_run", "vcm_batch_get_info",
                  "vcm_batch_destroy", "vcm_server_create", "vcm_submit", "vcm_poll", "vcm_wait",
-                 "vcm_server_drain", "vcm_server_get_stats", "vcm_server_reset_stats",
+                 "vcm_server_drain", "vcm_server_hold", "vcm_server_get_stats", "vcm_server_reset_stats",
                  "vcm_server_destroy", "vcm_tune_cell_size", "vcm_map_error", "vcm_error_bounds"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -495,6 +496,10 @@ class Server:
 
     def drain(self):
         _check(load_library().vcm_server_drain(self.handle))
+
+    def hold(self, on: bool = True):
+        """Hold launches (admitted requests queue) or release them."""
+        _check(load_library().vcm_server_hold(self.handle, int(bool(on))))
 
     def stats(self):
         s = vcm_server_stats()

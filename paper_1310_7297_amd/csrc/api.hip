@@ -203,6 +203,7 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
     g->count = count;
 
     *p = ParamDesc{};
+    p->region_r2 = T.kind == VCM_VIEWER ? double(t->rmax) * double(t->rmax) : HUGE_VAL;
     p->fov_axis = P.gaze == 0 ? T.normal_axis : std::abs(P.gaze) - 1;
     p->fov_sign = P.gaze == 0 ? T.normal_sign : (P.gaze > 0 ? 1 : -1);
     const double half_fov = P.fov_deg / 2.0;

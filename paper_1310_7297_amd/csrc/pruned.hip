@@ -236,6 +236,19 @@ __device__ double t_colour(const CellFrame &F, double D, double alpha, int iq, d
 }
 
 __device__ void colour_viewpoint(const PrunedArgs &A, int64_t vp, PrunedSums &sum) {
+    // the viewpoint's gate: from its decided block, or its smallest block's
+    // representative
+    const uint32_t gw = A.gate[vp];
+    const int vis = static_cast<int>(gw & 1023u), N = static_cast<int>((gw >> 10) & 1023u);
+    const bool fov = (gw >> 20) & 1u;
+    const bool shown = fov && N > 0 && vis > 0;   // some colour survives the gate
+    if (!shown && !A.sums) {
+        // colour 0, bin 0: no cell lookup (most viewpoints of a city map)
+        A.bin[vp] = 0;
+        if (A.c) A.c[vp] = 0.0f;
+        if (A.count) A.count[vp] = static_cast<uint16_t>(vis);
+        return;
+    }
     const int n0 = A.grid.n[0], n1 = A.grid.n[1];
     const int ii[3] = {static_cast<int>(vp % n0), static_cast<int>((vp / n0) % n1),
                        static_cast<int>(vp / (static_cast<int64_t>(n0) * n1))};
@@ -257,13 +270,6 @@ __device__ void colour_viewpoint(const PrunedArgs &A, int64_t vp, PrunedSums &su
     const double D = sqrt(r2 + h * h);
     const double alpha = atan2(h, sqrt(r2));
     const double rho = D * cos(alpha), hh = D * sin(alpha);
-
-    // the viewpoint's gate: from its decided block, or its smallest block's
-    // representative
-    const uint32_t gw = A.gate[vp];
-    const int vis = static_cast<int>(gw & 1023u), N = static_cast<int>((gw >> 10) & 1023u);
-    const bool fov = (gw >> 20) & 1u;
-    const bool shown = fov && N > 0 && vis > 0;   // some colour survives the gate
 
     const CellFrame &F = A.F;
     double craw = 0.0, ce = 0.0;

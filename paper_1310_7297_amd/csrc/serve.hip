@@ -12,207 +12,114 @@
 // overlapping on the device with the launches still running.  Completion is
 // observed through events; the budget is returned then.
 #include <algorithm>
-#include <atomic>
 #include <chrono>
-#include <cmath>
-#include <condition_variable>
-#include <deque>
-#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
+#include "serve_core.h"
 #include "vcm_internal.h"
 
 using namespace vcm;
 
 namespace {
 
-using Clock = std::chrono::steady_clock;
-
-struct Request {
+struct Payload {
     vcm_query query;
     vcm_result result;
-    size_t footprint = 0;
-    uint64_t viewpoints = 0;
-    Clock::time_point t_submit, t_launch, t_done;
-    bool done = false;
-    vcm_status status = VCM_OK;
-    std::string message;
 };
 
-struct Launch {
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-    std::vector<uint64_t> tickets;
-    bool busy = false;
-};
-
-}  // namespace
-
-struct vcm_server {
+// The device side of the engine: one stream and one completion event per
+// launch slot; a launch is one batched persistent launch of its requests.
+class HipExecutor final : public serve::Executor<Payload> {
+public:
     const Index *ix = nullptr;
     int device = 0;
-    vcm_server_opts opts{};
     Tuning tune;
+    std::vector<hipStream_t> stream;
+    std::vector<hipEvent_t> done;
 
-    std::mutex m;
-    std::condition_variable cv;
-    bool stop = false;
-    std::thread engine;
+    // The plan's buffer is allocated and freed in stream order.
+    vcm_status start(int slot, const std::vector<const Payload *> &batch, std::string *msg) override {
+        std::vector<vcm_query> qs;
+        std::vector<vcm_result> rs;
+        for (const Payload *p : batch) {
+            qs.push_back(p->query);
+            rs.push_back(p->result);
+        }
+        const hipStream_t s = stream[slot];
+        BatchPlan p;
+        p.device = device;
+        p.tune = tune;
+        vcm_status st = p.prepare(*ix, qs.data(), static_cast<int>(qs.size()), rs.data());
+        if (st == VCM_OK) {
+            p.layout();
+            const hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&p.d_base), p.bytes, s);
+            if (e != hipSuccess) st = set_error(VCM_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        }
+        if (st == VCM_OK) {
+            std::vector<char> img;
+            p.image(img);
+            st = upload(img.data(), img.size(), p.d_base, device, s);
+            if (st == VCM_OK) st = p.enqueue(s, nullptr);
+            hipFreeAsync(p.d_base, s);
+        }
+        if (st == VCM_OK && hipEventRecord(done[slot], s) != hipSuccess)
+            st = set_error(VCM_E_DEVICE, "event record failed");
+        if (st != VCM_OK) {
+            *msg = vcm_last_error();
+            hipStreamSynchronize(s);
+        }
+        return st;
+    }
 
-    uint64_t next_ticket = 1;
-    size_t used = 0;
-    std::unordered_map<uint64_t, Request> req;
-    std::deque<uint64_t> waiting;
-    std::vector<Launch> slots;
-
-    // statistics (completed requests)
-    std::vector<double> latency_ms;
-    uint64_t completed = 0, failed = 0, rejected = 0, launches = 0, vp_done = 0;
-    size_t peak_used = 0;
-    Clock::time_point t_first, t_last;
-    bool any = false;
+    vcm_status poll(int slot, std::string *msg) override {
+        const hipError_t q = hipEventQuery(done[slot]);
+        if (q == hipErrorNotReady) return VCM_E_PENDING;
+        if (q == hipSuccess) return VCM_OK;
+        *msg = std::string("launch failed: ") + hipGetErrorString(q);
+        return VCM_E_DEVICE;
+    }
 };
 
-namespace {
-
-// Device bytes a request holds while admitted.
-size_t footprint(const vcm_query &q, const vcm_result &r, uint64_t n) {
+// Device bytes a request holds while admitted: its result buffers, its work
+// record and, for the pruned methods, the workspace of the block hierarchy
+// (a gate word per viewpoint and the block lists of every level).
+size_t footprint(const vcm_query &q, const vcm_result &r, const GridDesc &g, int dim) {
+    const uint64_t n = static_cast<uint64_t>(g.count);
     size_t b = 0;
     if (r.bin) b += n;
     if (r.c) b += 4 * n;
     if (r.count) b += 2 * n;
     b += sizeof(BruteArgs) + 64;
-    if (q.params.method != VCM_BRUTE) {
-        const int th = std::max(1, q.params.theta_blocks);
-        uint64_t blocks = 1;
-        for (int k = 0; k < 3; ++k) blocks *= (static_cast<uint64_t>(std::max(q.grid.n[k], 1)) + th - 1) / th;
-        b += 4 * blocks;
-    }
+    if (q.params.method != VCM_BRUTE)
+        b += query_workspace(g, dim, q.params.method, std::max(1, q.params.theta_blocks), false).bytes;
     return b;
 }
 
-void finish(vcm_server *s, uint64_t t, vcm_status st, const std::string &msg) {
-    auto it = s->req.find(t);
-    if (it == s->req.end()) return;
-    Request &r = it->second;
-    r.done = true;
-    r.status = st;
-    r.message = msg;
-    r.t_done = Clock::now();
-    s->used -= r.footprint;
-    if (st == VCM_OK) {
-        ++s->completed;
-        s->vp_done += r.viewpoints;
-        s->latency_ms.push_back(std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count());
-        if (!s->any || r.t_submit < s->t_first) s->t_first = r.t_submit;
-        if (!s->any || r.t_done > s->t_last) s->t_last = r.t_done;
-        s->any = true;
-    } else {
-        ++s->failed;
-    }
+}  // namespace
+
+struct vcm_server {
+    const Index *ix = nullptr;
+    vcm_server_opts opts{};
+    HipExecutor ex;
+    serve::Core<Payload> *core = nullptr;
+    std::thread engine;
+};
+
+namespace {
+
+void release_slots(vcm_server *s) {
+    for (hipStream_t x : s->ex.stream)
+        if (x) hipStreamDestroy(x);
+    for (hipEvent_t x : s->ex.done)
+        if (x) hipEventDestroy(x);
 }
 
-// Enqueue one launch of the given requests on a slot's stream (engine thread,
-// lock held).  The plan's buffer is allocated and freed in stream order.
-void dispatch(vcm_server *s, Launch &L, std::vector<uint64_t> &&tk) {
-    std::vector<vcm_query> qs;
-    std::vector<vcm_result> rs;
-    for (uint64_t t : tk) {
-        Request &r = s->req[t];
-        r.t_launch = Clock::now();
-        qs.push_back(r.query);
-        rs.push_back(r.result);
-    }
-    BatchPlan p;
-    p.device = s->device;
-    p.tune = s->tune;
-    vcm_status st = p.prepare(*s->ix, qs.data(), static_cast<int>(qs.size()), rs.data());
-    if (st == VCM_OK) {
-        p.layout();
-        const hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&p.d_base), p.bytes, L.stream);
-        if (e != hipSuccess) st = set_error(VCM_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
-    }
-    if (st == VCM_OK) {
-        std::vector<char> img;
-        p.image(img);
-        st = upload(img.data(), img.size(), p.d_base, s->device, L.stream);
-        if (st == VCM_OK) st = p.enqueue(L.stream, nullptr);
-        hipFreeAsync(p.d_base, L.stream);
-    }
-    if (st == VCM_OK && hipEventRecord(L.done, L.stream) != hipSuccess)
-        st = set_error(VCM_E_DEVICE, "event record failed");
-    if (st != VCM_OK) {
-        const std::string msg = vcm_last_error();
-        hipStreamSynchronize(L.stream);
-        for (uint64_t t : tk) finish(s, t, st, msg);
-        return;
-    }
-    L.tickets = std::move(tk);
-    L.busy = true;
-    ++s->launches;
-}
-
-void engine_main(vcm_server *s) {
-    hipSetDevice(s->device);
-    std::unique_lock<std::mutex> lock(s->m);
-    for (;;) {
-        // completions
-        bool busy = false;
-        for (auto &L : s->slots) {
-            if (!L.busy) continue;
-            const hipError_t q = hipEventQuery(L.done);
-            if (q == hipErrorNotReady) {
-                busy = true;
-                continue;
-            }
-            const vcm_status st = q == hipSuccess ? VCM_OK : VCM_E_DEVICE;
-            const std::string msg = q == hipSuccess ? "" : std::string("launch failed: ") + hipGetErrorString(q);
-            for (uint64_t t : L.tickets) finish(s, t, st, msg);
-            L.tickets.clear();
-            L.busy = false;
-        }
-        if (s->stop) {
-            // shutting down: requests not yet launched are cancelled, the
-            // launches in flight are waited for
-            while (!s->waiting.empty()) {
-                finish(s, s->waiting.front(), VCM_E_INTERNAL, "cancelled: server shut down");
-                s->waiting.pop_front();
-            }
-            s->cv.notify_all();
-            if (!busy) break;
-        }
-        // new launches: every waiting request, up to max_batch per launch
-        for (auto &L : s->slots) {
-            if (s->waiting.empty()) break;
-            if (L.busy) continue;
-            std::vector<uint64_t> tk;
-            while (!s->waiting.empty() && static_cast<int>(tk.size()) < s->opts.max_batch) {
-                tk.push_back(s->waiting.front());
-                s->waiting.pop_front();
-            }
-            dispatch(s, L, std::move(tk));
-            busy = busy || L.busy;
-        }
-        s->cv.notify_all();  // completions wake waiters
-        if (busy)
-            s->cv.wait_for(lock, std::chrono::microseconds(50));
-        else
-            s->cv.wait(lock, [s] { return s->stop || !s->waiting.empty(); });
-    }
-    s->cv.notify_all();
-}
-
-double percentile(std::vector<double> v, double p) {
-    if (v.empty()) return 0.0;
-    std::sort(v.begin(), v.end());
-    // nearest rank
-    size_t k = static_cast<size_t>(std::ceil(p / 100.0 * v.size()));
-    k = std::min(std::max<size_t>(k, 1), v.size());
-    return v[k - 1];
+vcm_status finish_status(vcm_status st, const std::string &msg) {
+    if (st == VCM_OK || st == VCM_E_PENDING) return st;
+    return set_error(st, msg);
 }
 
 }  // namespace
@@ -240,24 +147,34 @@ vcm_status vcm_server_create(const vcm_index *index, const vcm_server_opts *opts
     vcm_server *s = new (std::nothrow) vcm_server;
     if (!s) return set_error(VCM_E_NOMEM, "host allocation failed");
     s->ix = &ix;
-    s->device = ix.device;
     s->opts = o;
-    if (o.chunk) s->tune.chunk = o.chunk;
-    if (o.blocks_per_cu) s->tune.blocks_per_cu = o.blocks_per_cu;
+    s->ex.ix = &ix;
+    s->ex.device = ix.device;
+    if (o.chunk) s->ex.tune.chunk = o.chunk;
+    if (o.blocks_per_cu) s->ex.tune.blocks_per_cu = o.blocks_per_cu;
     device_cus(ix.device);
-    s->slots.resize(o.max_inflight);
-    for (auto &L : s->slots) {
-        if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) {
-            for (auto &x : s->slots) {
-                if (x.stream) hipStreamDestroy(x.stream);
-                if (x.done) hipEventDestroy(x.done);
-            }
+    s->ex.stream.assign(o.max_inflight, nullptr);
+    s->ex.done.assign(o.max_inflight, nullptr);
+    for (int i = 0; i < o.max_inflight; ++i) {
+        if (hipStreamCreateWithFlags(&s->ex.stream[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s->ex.done[i], hipEventDisableTiming) != hipSuccess) {
+            release_slots(s);
             delete s;
             return set_error(VCM_E_DEVICE, "stream or event creation failed");
         }
     }
-    s->engine = std::thread(engine_main, s);
+    s->core = new (std::nothrow) serve::Core<Payload>(o.mem_budget_bytes, o.max_inflight, o.max_batch, &s->ex);
+    if (!s->core) {
+        release_slots(s);
+        delete s;
+        return set_error(VCM_E_NOMEM, "host allocation failed");
+    }
+    const int dev = ix.device;
+    serve::Core<Payload> *core = s->core;
+    s->engine = std::thread([dev, core] {
+        hipSetDevice(dev);
+        core->run();
+    });
     *out = s;
     return VCM_OK;
 }
@@ -276,128 +193,93 @@ vcm_status vcm_submit(vcm_server *server, const vcm_query *query, const vcm_resu
     if (st != VCM_OK) return st;
     if (g.count >= (int64_t(1) << 31)) return set_error(VCM_E_INVALID, "grid too large to serve");
     const uint64_t n = static_cast<uint64_t>(g.count);
-    const size_t f = footprint(*query, *result, n);
-    std::lock_guard<std::mutex> lock(server->m);
-    if (server->stop) return set_error(VCM_E_INVALID, "server is shutting down");
-    if (f > server->opts.mem_budget_bytes)
-        return set_error(VCM_E_INVALID, "request needs " + std::to_string(f) + " bytes, more than the whole budget");
-    if (server->used + f > server->opts.mem_budget_bytes) {
-        ++server->rejected;
-        return set_error(VCM_E_AGAIN, "memory budget in use; retry later");
-    }
-    server->used += f;
-    server->peak_used = std::max(server->peak_used, server->used);
-    const uint64_t tk = server->next_ticket++;
-    Request &r = server->req[tk];
-    r.query = *query;
-    r.result = *result;
-    r.footprint = f;
-    r.viewpoints = n;
-    r.t_submit = Clock::now();
-    server->waiting.push_back(tk);
-    server->cv.notify_all();
-    *ticket = tk;
-    return VCM_OK;
+    std::string msg;
+    st = server->core->submit(Payload{*query, *result}, footprint(*query, *result, g, server->ix->dim), n, ticket,
+                              &msg);
+    return finish_status(st, msg);
 }
 
 vcm_status vcm_poll(vcm_server *server, uint64_t ticket, vcm_request_info *info) {
     clear_error();
     if (!server) return set_error(VCM_E_INVALID, "null server");
-    std::lock_guard<std::mutex> lock(server->m);
-    auto it = server->req.find(ticket);
-    if (it == server->req.end()) return set_error(VCM_E_NOTFOUND, "unknown ticket");
-    Request &r = it->second;
-    if (!r.done) return VCM_E_PENDING;
-    if (info) {
-        info->latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
-        info->queue_ms = std::chrono::duration<double, std::milli>(r.t_launch - r.t_submit).count();
-        info->viewpoints = r.viewpoints;
+    serve::RequestInfo ri;
+    std::string msg;
+    const vcm_status st = server->core->poll(ticket, &ri, &msg);
+    if (info && st != VCM_E_PENDING && st != VCM_E_NOTFOUND) {
+        info->latency_ms = ri.latency_ms;
+        info->queue_ms = ri.queue_ms;
+        info->viewpoints = ri.viewpoints;
     }
-    const vcm_status st = r.status;
-    const std::string msg = r.message;
-    server->req.erase(it);
-    if (st != VCM_OK) return set_error(st, msg);
-    return VCM_OK;
+    return finish_status(st, msg);
 }
 
 vcm_status vcm_wait(vcm_server *server, uint64_t ticket, int32_t timeout_ms, vcm_request_info *info) {
     clear_error();
     if (!server) return set_error(VCM_E_INVALID, "null server");
-    {
-        std::unique_lock<std::mutex> lock(server->m);
-        auto ready = [&] {
-            auto it = server->req.find(ticket);
-            return it == server->req.end() || it->second.done;
-        };
-        if (timeout_ms < 0)
-            server->cv.wait(lock, ready);
-        else
-            server->cv.wait_for(lock, std::chrono::milliseconds(timeout_ms), ready);
+    serve::RequestInfo ri;
+    std::string msg;
+    const vcm_status st = server->core->wait(ticket, timeout_ms, &ri, &msg);
+    if (info && st != VCM_E_PENDING && st != VCM_E_NOTFOUND) {
+        info->latency_ms = ri.latency_ms;
+        info->queue_ms = ri.queue_ms;
+        info->viewpoints = ri.viewpoints;
     }
-    return vcm_poll(server, ticket, info);
+    return finish_status(st, msg);
 }
 
 vcm_status vcm_server_drain(vcm_server *server) {
     clear_error();
     if (!server) return set_error(VCM_E_INVALID, "null server");
-    std::unique_lock<std::mutex> lock(server->m);
-    server->cv.wait(lock, [&] {
-        if (!server->waiting.empty()) return false;
-        for (auto &L : server->slots)
-            if (L.busy) return false;
-        return true;
-    });
+    server->core->drain();
+    return VCM_OK;
+}
+
+vcm_status vcm_server_hold(vcm_server *server, int32_t hold) {
+    clear_error();
+    if (!server) return set_error(VCM_E_INVALID, "null server");
+    server->core->hold(hold != 0);
     return VCM_OK;
 }
 
 vcm_status vcm_server_get_stats(vcm_server *server, vcm_server_stats *out) {
     clear_error();
     if (!server || !out) return set_error(VCM_E_INVALID, "null argument");
-    std::lock_guard<std::mutex> lock(server->m);
-    out->completed = server->completed;
-    out->failed = server->failed;
-    out->rejected = server->rejected;
-    out->launches = server->launches;
-    out->viewpoints = server->vp_done;
-    out->p50_ms = percentile(server->latency_ms, 50.0);
-    out->p99_ms = percentile(server->latency_ms, 99.0);
-    out->max_ms = server->latency_ms.empty() ? 0.0
-                                             : *std::max_element(server->latency_ms.begin(), server->latency_ms.end());
-    const double span = server->any ? std::chrono::duration<double>(server->t_last - server->t_first).count() : 0.0;
-    out->requests_per_s = span > 0 ? server->completed / span : 0.0;
-    out->viewpoints_per_s = span > 0 ? server->vp_done / span : 0.0;
-    out->mem_in_use = server->used;
-    out->mem_peak = server->peak_used;
-    out->mem_budget = server->opts.mem_budget_bytes;
+    const serve::Stats s = server->core->stats();
+    out->completed = s.completed;
+    out->failed = s.failed;
+    out->rejected = s.rejected;
+    out->launches = s.launches;
+    out->viewpoints = s.viewpoints;
+    out->p50_ms = s.p50_ms;
+    out->p99_ms = s.p99_ms;
+    out->max_ms = s.max_ms;
+    out->requests_per_s = s.requests_per_s;
+    out->viewpoints_per_s = s.viewpoints_per_s;
+    out->mem_in_use = s.mem_in_use;
+    out->mem_peak = s.mem_peak;
+    out->mem_budget = s.mem_budget;
     return VCM_OK;
 }
 
 vcm_status vcm_server_reset_stats(vcm_server *server) {
     clear_error();
     if (!server) return set_error(VCM_E_INVALID, "null server");
-    std::lock_guard<std::mutex> lock(server->m);
-    server->latency_ms.clear();
-    server->completed = server->failed = server->rejected = server->launches = server->vp_done = 0;
-    server->peak_used = server->used;
-    server->any = false;
+    server->core->reset_stats();
     return VCM_OK;
 }
 
 vcm_status vcm_server_destroy(vcm_server *server) {
     clear_error();
     if (!server) return VCM_OK;
-    {
-        std::lock_guard<std::mutex> lock(server->m);
-        server->stop = true;
-        server->cv.notify_all();
-    }
+    server->core->stop();
     if (server->engine.joinable()) server->engine.join();
-    DeviceGuard guard(server->device);
-    for (auto &L : server->slots) {
-        if (L.stream) hipStreamSynchronize(L.stream);
-        if (L.stream) hipStreamDestroy(L.stream);
-        if (L.done) hipEventDestroy(L.done);
+    {
+        DeviceGuard guard(server->ex.device);
+        for (hipStream_t x : server->ex.stream)
+            if (x) hipStreamSynchronize(x);
+        release_slots(server);
     }
+    delete server->core;
     delete server;
     return VCM_OK;
 }

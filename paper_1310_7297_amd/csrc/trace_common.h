@@ -125,10 +125,24 @@ __device__ inline bool in_wedge(const TargetDesc &T, const ParamDesc &P, const f
 }
 
 // Viewpoints outside the field of view or outside the covered region are
-// obstructed.
+// obstructed.  One pass computes both (P.region_r2 is d_max^2 for a
+// viewer-centric map, +inf otherwise): the same decisions as in_region and
+// in_wedge, with fewer registers live in the ray kernels.
 template <int DIM>
 __device__ inline bool in_fov(const TargetDesc &T, const ParamDesc &P, const float *q) {
-    return in_region<DIM>(T, q) && in_wedge<DIM>(T, P, q);
+    if (P.fov_kind == kFovAll && !(P.region_r2 < HUGE_VAL)) return true;   // no wedge, no ball
+    double d2 = 0.0, dn = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const double d = double(q[k]) - double(T.c[k]);
+        d2 += d * d;
+        if (k == P.fov_axis) dn = P.fov_sign * d;
+    }
+    if (!(d2 <= P.region_r2)) return false;
+    if (P.fov_kind == kFovAll) return true;
+    if (P.fov_kind == kFovHalf) return dn >= 0.0;
+    if (P.fov_kind == kFovNarrow) return dn >= 0.0 && dn * dn >= P.fov_c2 * d2;
+    return dn >= 0.0 || dn * dn <= P.fov_c2 * d2;
 }
 
 

@@ -84,6 +84,7 @@ enum FovKind : int32_t { kFovAll = 0, kFovHalf = 1, kFovNarrow = 2, kFovWide = 3
 
 struct ParamDesc {
     double fov_c2;      // cos^2 of the half angle (exact for the table's FOVs)
+    double region_r2;   // viewer-centric maps: d_max^2 (the covered ball); else +inf
     int32_t fov_axis;   // axis and orientation of the wedge
     int32_t fov_sign;
     int32_t fov_kind;

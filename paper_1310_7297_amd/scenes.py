@@ -173,6 +173,49 @@ def city(extent: float, n_boxes: int, seed: int, side=(20.0, 80.0),
     return Scene(3, lo, hi)
 
 
+def city_zipf(extent: float, n_boxes: int, seed: int, side=(20.0, 80.0), districts: int = 32,
+              s: float = 1.0, targets: Sequence[Target] = (), clearance: float = 5.0) -> Scene:
+    """Box city whose density follows a Zipf law over districts: the space is
+    cut into districts x districts squares, ranked in a seeded random order,
+    and each box falls in the district of rank r with probability
+    proportional to 1 / r**s, uniformly inside it.  Per box, in this order:
+    district, offset x, offset y, width, depth, then the lognormal height (as
+    in `city`).  Boxes within `clearance` of any target are dropped."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    order = rng.permutation(districts * districts)
+    w_rank = 1.0 / np.arange(1, districts * districts + 1, dtype=np.float64) ** s
+    prob = np.empty_like(w_rank)
+    prob[order] = w_rank / w_rank.sum()
+    d = rng.choice(districts * districts, size=n_boxes, p=prob)
+    u = rng.random((n_boxes, 4))
+    z = rng.standard_normal(n_boxes)
+    step = extent / districts
+    cx = quantize((d % districts + u[:, 0]) * step)
+    cy = quantize((d // districts + u[:, 1]) * step)
+    w = quantize(side[0] + u[:, 2] * (side[1] - side[0]))
+    dd = quantize(side[0] + u[:, 3] * (side[1] - side[0]))
+    h = np.maximum(quantize(np.exp(_MU_LN + _SIGMA_LN * z)), QUANTUM)
+    lo = np.stack([quantize(cx - w / 2), quantize(cy - dd / 2), np.zeros(n_boxes)])
+    hi = np.stack([quantize(cx + w / 2), quantize(cy + dd / 2), h])
+    lo, hi = _drop_near_target(lo, hi, targets, clearance)
+    return Scene(3, lo, hi)
+
+
+def sweep_billboard(n_boxes: int = 20000, dist: str = "uniform", seed: int = 3):
+    """Workload of the parameter sweeps (Table 2's parameters on a 3-D city):
+    a 4 km city of `n_boxes` boxes (uniform or Zipf-clustered), a 30 m x 15 m
+    billboard facing +y at the centre, 256 x 256 x 64 viewpoints over
+    0-150 m, field of view 120 degrees (the paper's default), 16 bins."""
+    t = Target(BILLBOARD, (2000.0, 2000.0, 10.0), (30.0, 15.0), normal_axis=1, normal_sign=1,
+               samples_u=16, samples_v=8)
+    if dist == "uniform":
+        scene = city(4000.0, n_boxes, seed=seed, targets=[t])
+    else:
+        scene = city_zipf(4000.0, n_boxes, seed=seed, targets=[t])
+    g = Grid((0.0, 0.0, 0.0), (4000.0, 4000.0, 150.0), (256, 256, 64))
+    return scene, Query(t, g, Params(n_bins=16, fov_deg=120.0))
+
+
 def plain_2d(extent: float, n_rects: int, seed: int, side=(10.0, 50.0),
              targets: Sequence[Target] = (), clearance: float = 5.0,
              max_tries: int = 100000) -> Scene:

@@ -1,6 +1,6 @@
 """Comparison of the HIP path's outputs with the oracle's, to the stated bar:
 visible counts bit-exact; colour bins bit-exact except where the oracle's
-colour (in the bin's scale) lies within 1e-6 of a bin edge; colours within
+colour (in the bin's scale) lies within 1e-6 of an interior bin edge; colours within
 1e-5 relative of the oracle's, with an absolute floor of 1e-9."""
 import math
 
@@ -14,8 +14,12 @@ EDGE = 1e-6
 
 
 def near_edge(cb, n_bins):
+    """Colours (in the bin's scale) within 1e-6 of an interior bin edge k/B,
+    0 < k < B: only there can two correct roundings fall in different bins
+    (0 and 1 decide no bin: bin = min(B - 1, floor(c B)))."""
     x = np.asarray(cb, dtype=np.float64) * n_bins
-    return np.abs(x - np.round(x)) < EDGE * n_bins
+    k = np.round(x)
+    return (np.abs(x - k) < EDGE * n_bins) & (k >= 1) & (k <= n_bins - 1)
 
 
 def compare(gpu, orc, n_bins, idx=None, label=""):

@@ -83,32 +83,32 @@ def test_served_results_equal_solo():
 
 
 def test_waiting_requests_share_one_launch():
-    """With one launch allowed in flight, requests submitted while a long
-    request runs all wait, and the next launch takes them together."""
+    """Requests admitted while launches are held go out together when
+    released: one launch for eight requests with max_batch 64, three with
+    max_batch 3 (submission order, a launch per slot at a time); every
+    result equals the request computed alone."""
     scene, targets = mixed_scene()
     qs, prec = mixed_queries(targets)
-    small = qs[:8]
+    small, sp = qs[:8], prec[:8]
     idx = vcm.vcm_build_index(scene)
-    solo = [_solo(idx, q, p) for q, p in zip(small, prec[:8])]
-    big = scenes.Query(targets[4], scenes.Grid((0.0, 0.0, 0.0), (512.0, 512.0, 128.0), (256, 256, 64)),
-                       scenes.Params(n_bins=16, mode=scenes.FRACTION))
-    srv = vcm.Server(idx, max_inflight=1, max_batch=64)
-    rb = vcm.alloc_result(big.grid.count)
-    t0 = time.perf_counter()
-    tb = srv.submit(big, rb, precision=vcm.VCM_FP64)
-    res = [vcm.alloc_result(q.grid.count) for q in small]
-    tickets = [srv.submit(q, r, precision=p) for q, r, p in zip(small, res, prec[:8])]
-    submit_s = time.perf_counter() - t0
-    info = srv.wait(tb, 60000)
-    for t in tickets:
-        assert srv.wait(t, 60000) is not None
-    st = srv.stats()
-    assert st["completed"] == 9 and st["failed"] == 0
-    if info["latency_ms"] > 1e3 * submit_s:  # the long request outlived the submits
-        assert st["launches"] == 2, st
-    for i, (a, b) in enumerate(zip(solo, res)):
-        _same(a, b, f"request {i}")
-    srv.close()
+    solo = [_solo(idx, q, p) for q, p in zip(small, sp)]
+    for max_batch, launches in ((64, 1), (3, 3)):
+        srv = vcm.Server(idx, max_inflight=1, max_batch=max_batch)
+        srv.hold(True)
+        res = [vcm.alloc_result(q.grid.count) for q in small]
+        tickets = [srv.submit(q, r, precision=p) for q, r, p in zip(small, res, sp)]
+        assert all(t is not None for t in tickets)
+        time.sleep(0.01)
+        assert srv.stats()["launches"] == 0
+        srv.hold(False)
+        for t in tickets:
+            assert srv.wait(t, 60000) is not None
+        st = srv.stats()
+        assert st["completed"] == 8 and st["failed"] == 0
+        assert st["launches"] == launches, st
+        for i, (a, b) in enumerate(zip(solo, res)):
+            _same(a, b, f"request {i} (max_batch {max_batch})")
+        srv.close()
     idx.free()
 
 
