@@ -16,14 +16,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic lane-operations per unit of work: one float32 slab test of a ray
-# against a box; one corridor column visit; one box record examined by a
-# column scan (its top against the floor, its extent across the walk and its
-# bottom against the slice: four differences, two ors, two compares); one
-# candidate record checked against the corridor over its own extent along the
-# walk (clip, two parameter bounds with margins, four extents, four compares).
+# Algorithmic lane-operations per unit of work (the roofline's useful work):
+# one float32 slab test of a ray against a box (6 subtractions or products,
+# 3 min, 3 max, max3/min3, clamps and compares: 20); one corridor column
+# visited (12).  The headline fraction counts these only.
 OPS_PER_BOX_TEST = 20
 OPS_PER_COLUMN = 12
+# This implementation's own culling, reported beside the headline: one box
+# record examined by a column scan (four differences, two ors, two compares)
+# and one candidate checked against the corridor over its own extent along
+# the walk (clip, two parameter bounds with margins, four extents, four
+# compares).
 OPS_PER_RECORD = 8
 OPS_PER_NARROW_TEST = 30
 # MI355X: 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz (non-packed lane ops).
@@ -36,7 +39,10 @@ PEAK_HBM = 8.0e12
 PROFILE = os.path.join(ROOT, "profiles", "k_brute_city20k_cube_fraction.md")
 TRAFFIC_BYTES = 87600525
 TRAFFIC_CELL = 128.0
-KERNEL_SOURCES = ("brute.hip", "index.hip", "vcm_internal.h")
+KERNEL_SOURCES = ("brute.hip", "trace_common.h", "index.hip", "vcm_internal.h")
+# Issue counters of the same profile (per launch), valid under the same hash.
+PROFILE_VALU = {"fraction": 2.740e9, "full": 6.827e8}
+CUS, CLOCK = 256, 2.4e9
 
 
 def kernel_sources_hash() -> str:
@@ -48,15 +54,52 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, mode: str, cell: float):
-    """The profiled HBM bytes, or None if the workload or the kernel differs."""
-    if workload != "cube" or mode != "fraction" or cell != TRAFFIC_CELL:
-        return None
+def profile_valid(workload: str, cell: float) -> bool:
+    """The committed profile covers this workload, index width and kernel sources."""
+    if workload != "cube" or cell != TRAFFIC_CELL:
+        return False
     try:
         text = open(PROFILE).read()
     except OSError:
+        return False
+    return kernel_sources_hash() in text
+
+
+def measured_traffic(workload: str, mode: str, cell: float):
+    """The profiled HBM bytes, or None if the workload or the kernel differs."""
+    if mode != "fraction" or not profile_valid(workload, cell):
         return None
-    return TRAFFIC_BYTES if kernel_sources_hash() in text else None
+    return TRAFFIC_BYTES
+
+
+def roofline_of(st, kernel_ms):
+    """Useful-work roofline of one ray-kernel launch from its statistics."""
+    ops = OPS_PER_BOX_TEST * st["box_tests"] + OPS_PER_COLUMN * st["columns"]
+    cull = OPS_PER_RECORD * st["records"] + OPS_PER_NARROW_TEST * st["narrow_tests"]
+    t = kernel_ms * 1e-3
+    return {"achieved": ops / t / 1e12, "frac": ops / t / PEAK_LANE_OPS, "lane_ops_per_launch": ops,
+            "with_culling": {"lane_ops_per_launch": ops + cull, "achieved": (ops + cull) / t / 1e12,
+                             "frac": (ops + cull) / t / PEAK_LANE_OPS}}
+
+
+def oracle_agreement(gpu, orc, n_bins):
+    """The timed map against the float64 oracle on the same viewpoints: counts
+    exact; bins exact except where the oracle's colour is within 1e-6 of a bin
+    edge; colours within 1e-5 relative (1e-9 absolute floor)."""
+    import numpy as np
+    cnt = np.count_nonzero(gpu["count"].astype(np.int64) != orc["count"].astype(np.int64))
+    x = orc["cb"] * n_bins
+    k = np.round(x)
+    edge = (np.abs(x - k) < 1e-6 * n_bins) & (k >= 1) & (k <= n_bins - 1)   # interior bin edges
+    bins = np.count_nonzero((gpu["bin"] != orc["bin"]) & ~edge)
+    err = np.abs(gpu["c"].astype(np.float64) - orc["c"])
+    rel = err / np.maximum(np.abs(orc["c"]), 1e-30)
+    out = np.count_nonzero(err > 1e-5 * np.abs(orc["c"]) + 1e-9)
+    return {"viewpoints": int(len(orc["count"])), "count_mismatches": int(cnt),
+            "bin_mismatches_off_edge": int(bins), "edge_viewpoints_skipped": int(edge.sum()),
+            "colour_out_of_tolerance": int(out),
+            "max_rel_colour_error": float(np.max(np.where(orc["c"] > 0, rel, 0.0), initial=0.0)),
+            "tolerance": "count exact; bins exact off 1e-6 of interior edges; colour 1e-5 relative + 1e-9"}
 
 
 def parse():
@@ -67,9 +110,10 @@ def parse():
     ap.add_argument("--workload", default="cube", choices=("cube", "billboard"),
                     help="cube: 4 km city, 20,000 boxes, 30 m cube; billboard: 2 km city, 5,000 boxes")
     ap.add_argument("--mode", default="fraction", choices=("fraction", "full"))
-    ap.add_argument("--cell", type=float, default=-1.0,
-                    help="index column width; -1 (default): autotuned over 32/64/128 m for this "
-                         "workload; 0: the library's automatic width")
+    ap.add_argument("--cell", type=float, default=128.0,
+                    help="index column width (default 128 m: what the index autotuner picks for the "
+                         "4 km cube map, within 0.1%% of 256 m); -1: run the autotuner over 32-256 m "
+                         "first; 0: the library's automatic width")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
@@ -77,7 +121,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg (256 targets, 6.4 km city)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg (8 km city, Poisson arrivals)")
     ap.add_argument("--no-pruned", action="store_true", help="skip the pruned-construction leg")
-    ap.add_argument("--serve-requests", type=int, default=240)
+    ap.add_argument("--no-index", action="store_true", help="skip the index-build leg (100,000 boxes)")
+    ap.add_argument("--no-sweeps", action="store_true", help="skip the parameter sweeps (mu, theta, FOV, obstacles)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per arrival rate of the serving leg (2,000 as configured)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -117,9 +164,12 @@ def timed_steps(vcm, idx, q, bufs, steps, warmup):
 
 def bench_pruned(vcm, idx, q):
     """4 km cube map: the pruned construction (VCM_E, VCM_M, VCM_T) beside the
-    brute-force map, FULL mode (the paper's rule): time per map, the Sec. V-A
-    error of VCM_E against the brute force and of VCM_M / VCM_T against
-    VCM_E, the Sec. IV-A bounds, and VCM_E over minimum block sizes."""
+    brute-force map, in both modes.  Per method: time per map (visible-region
+    blocks, the traced representatives of the undecided smallest blocks, and
+    the cell colouring), the blocks decided and traced, the Sec. V-A error of
+    VCM_E against the brute force and of VCM_M / VCM_T against VCM_E, and the
+    Sec. IV-A bound beside the error it covers measured over the grid; then
+    VCM_E over minimum block sizes."""
     import torch
     from paper_1310_7297_amd import scenes
     n = q.grid.count
@@ -129,7 +179,7 @@ def bench_pruned(vcm, idx, q):
 
     def run(qq, reps=3):
         r = vcm.alloc_result(n)
-        vcm.vcm_compute(idx, qq, *r)
+        st = vcm.vcm_compute(idx, qq, *r, stats=True)
         torch.cuda.synchronize()
         ms = []
         for _ in range(reps):
@@ -139,23 +189,30 @@ def bench_pruned(vcm, idx, q):
             e1.record()
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
-        return r, min(ms)
+        return r, min(ms), st
 
-    brute, t_b = run(with_(mode=scenes.FULL, method=scenes.BRUTE))
-    out = {"mode": "full", "brute_ms": t_b, "methods": {}, "theta": {}}
-    maps = {}
-    for name, m in (("E", scenes.PRUNED_E), ("M", scenes.PRUNED_M), ("T", scenes.PRUNED_T)):
-        r, t = run(with_(mode=scenes.FULL, method=m))
-        maps[name] = r
-        ref = brute if name == "E" else maps["E"]
-        err = vcm.vcm_map_error(ref[1], r[1])
-        out["methods"][name] = {"ms": t, "error_vs": "brute" if name == "E" else "E",
-                                "error_signed": err[0], "error_abs": err[1]}
-    out["bounds"] = vcm.vcm_error_bounds(q, 3)
-    for th in (2, 4, 8, 16):
-        r, t = run(with_(mode=scenes.FULL, method=scenes.PRUNED_E, theta_blocks=th))
-        err = vcm.vcm_map_error(maps["E"][1], r[1])
-        out["theta"][str(th)] = {"ms": t, "error_signed_vs_theta1": err[0], "error_abs_vs_theta1": err[1]}
+    out = {}
+    for mode_name, mode in (("full", scenes.FULL), ("fraction", scenes.FRACTION)):
+        _, t_b, _ = run(with_(mode=mode, method=scenes.BRUTE))
+        leg = {"brute_ms": t_b, "methods": {}, "theta": {}}
+        maps = {}
+        for name, m in (("E", scenes.PRUNED_E), ("M", scenes.PRUNED_M), ("T", scenes.PRUNED_T)):
+            r, t, st = run(with_(mode=mode, method=m))
+            maps[name] = r
+            d = {"ms": t, "vs_brute": t_b / t, "blocks": st["blocks"], "blocks_decided": st["blocks_decided"],
+                 "traced_viewpoints": st["leaves"], "error_vs": "brute" if name == "E" else "E",
+                 "error_signed": st["err_signed"], "error_abs": st["err_abs"]}
+            if name != "E":
+                d.update({"bound": st["bound"], "bound_measured": st["bound_measured"],
+                          "bound_ratio": st["bound_measured"] / st["bound"] if st["bound"] > 0 else None})
+            leg["methods"][name] = d
+        for th in (2, 4, 8, 16):
+            r, t, st = run(with_(mode=mode, method=scenes.PRUNED_E, theta_blocks=th))
+            err = vcm.vcm_map_error(maps["E"][1], r[1])
+            leg["theta"][str(th)] = {"ms": t, "vs_brute": t_b / t, "blocks": st["blocks"],
+                                     "blocks_decided": st["blocks_decided"], "traced_blocks": st["leaves"],
+                                     "error_signed_vs_theta1": err[0], "error_abs_vs_theta1": err[1]}
+        out[mode_name] = leg
     return out
 
 
@@ -235,7 +292,9 @@ def bench_serve(n_req: int):
            "requests": n_req, "mean_viewpoints": n_vp / n_req,
            "sequential_requests_per_s": n_req / t_seq, "index_cell_tuning": tuning, "rates": []}
     srv = vcm.Server(idx, max_inflight=2, max_batch=64)
-    for rate in (100.0, 250.0, 500.0, 1000.0, 4000.0, 16000.0):
+    # the configured arrival rates, then higher ones to find where the server
+    # stops keeping up (achieved below 95 % of offered)
+    for rate in (50.0, 100.0, 200.0, 500.0, 1000.0, 2000.0, 4000.0, 8000.0, 16000.0):
         srv.reset_stats()
         arr = scenes.poisson_arrivals(rate, n_req, 55)
         tickets = []
@@ -267,7 +326,101 @@ def bench_serve(n_req: int):
               f"p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
     srv.close()
     idx.free()
+    keeps = [r["offered_req_per_s"] for r in out["rates"] if r["requests_per_s"] >= 0.95 * r["offered_req_per_s"]]
+    out["saturation_req_per_s"] = max(r["requests_per_s"] for r in out["rates"])
+    out["highest_rate_kept_up"] = max(keeps) if keeps else None
     return out
+
+
+def bench_sweeps(cell: float = 64.0):
+    """The paper's parameter sweeps (Table 2) on the synthetic 3-D city, as
+    trend checks of VCM_E, VCM_M and VCM_T (FULL mode, the paper's rule):
+    angular resolution mu, minimum block size theta, field of view, and the
+    number of obstacles with uniform and Zipf-clustered placement.  Per
+    setting: time per map of each method and of the brute force, the Sec. V-A
+    error of VCM_M / VCM_T against VCM_E and of VCM_E against the brute
+    force (theta: against VCM_E at theta = 1), and the visible fraction."""
+    import torch
+    import paper_1310_7297_amd as vcm
+    from paper_1310_7297_amd import scenes
+
+    def timed(idx, q, r):
+        st = vcm.vcm_compute(idx, q, *r, stats=True)
+        ms = []
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            vcm.vcm_compute(idx, q, *r)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return min(ms), st
+
+    def with_(q, **kw):
+        return scenes.Query(q.target, q.grid, scenes.Params(**{**q.params.__dict__, **kw}))
+
+    def methods(idx, q):
+        n = q.grid.count
+        rb, r = vcm.alloc_result(n), {m: vcm.alloc_result(n) for m in "EMT"}
+        tb, _ = timed(idx, with_(q, method=scenes.BRUTE), rb)
+        out = {"brute_ms": tb}
+        for m, code in (("E", scenes.PRUNED_E), ("M", scenes.PRUNED_M), ("T", scenes.PRUNED_T)):
+            t, st = timed(idx, with_(q, method=code), r[m])
+            out[m] = {"ms": t, "error_signed": st["err_signed"], "error_abs": st["err_abs"]}
+        cnt = rb[2].cpu().numpy().view("uint16")
+        out["visible_fraction"] = float((cnt > 0).mean())
+        return out, r
+
+    res = {"workload": "sweep_billboard: 4 km city, 30 x 15 m billboard, 256x256x64 viewpoints, "
+                       "FOV 120 (defaults: 20,000 uniform boxes, mu 4', theta 1)", "mode": "full"}
+    scene, q = scenes.sweep_billboard()
+    idx = vcm.vcm_build_index(scene, cell_size=cell)
+    res["mu"] = {}
+    for mu in (1.0, 2.0, 4.0, 8.0, 16.0):
+        res["mu"][str(int(mu))], _ = methods(idx, with_(q, mu_arcmin=mu))
+    res["theta"] = {}
+    _, base = methods(idx, q)
+    for th in (2, 4, 8, 16):
+        r = vcm.alloc_result(q.grid.count)
+        t, st = timed(idx, with_(q, method=scenes.PRUNED_E, theta_blocks=th), r)
+        err = vcm.vcm_map_error(base["E"][1], r[1])
+        res["theta"][str(th)] = {"E_ms": t, "error_signed_vs_theta1": err[0], "error_abs_vs_theta1": err[1],
+                                 "blocks": st["blocks"], "traced_viewpoints": st["leaves"]}
+    res["fov"] = {}
+    for fov in (60.0, 120.0, 180.0, 240.0, 300.0, 360.0):
+        res["fov"][str(int(fov))], _ = methods(idx, with_(q, fov_deg=fov))
+    idx.free()
+    res["obstacles"] = {}
+    for dist in ("uniform", "zipf"):
+        for n in (5000, 10000, 15000, 20000, 25000):
+            sc, qq = scenes.sweep_billboard(n, dist)
+            idx = vcm.vcm_build_index(sc, cell_size=cell)
+            res["obstacles"][f"{dist}_{n // 1000}k"], _ = methods(idx, qq)
+            idx.free()
+    return res
+
+
+def bench_index():
+    """Index build at scale: the 100,000-box 8 km city at column widths of 16
+    to 256 m (device time of the build kernels, wall time of the whole build
+    including the host's copies)."""
+    import paper_1310_7297_amd as vcm
+    from paper_1310_7297_amd import scenes
+    scene, _ = scenes.city8km_serving(n_requests=1)
+    vcm.vcm_build_index(scene, cell_size=64.0).free()    # first launch of the build kernels
+    out = []
+    for cs in (16.0, 32.0, 64.0, 128.0, 256.0):
+        kms, wall = [], []
+        for _ in range(3):
+            idx = vcm.vcm_build_index(scene, cell_size=cs)
+            info = idx.info()
+            kms.append(info["kernel_ms"])
+            wall.append(info["build_ms"])
+            idx.free()
+        out.append({"cell_size": cs, "columns": info["nx"] * info["ny"], "refs": info["n_refs"],
+                    "longest_list": info["longest_list"], "kernel_ms": min(kms), "build_ms": min(wall),
+                    "device_bytes": info["device_bytes"]})
+    return {"workload": "city8km_serving scene: 100,000 boxes, 8 km", "boxes": scene.n, "cells": out}
 
 
 def main():
@@ -290,12 +443,10 @@ def main():
     q.params.mode = mode
     n_vp = q.grid.count
 
-    tuning = None
-    cell = args.cell
-    if cell < 0:
-        # index autotuner (untimed set-up): fastest column width for this map
-        tuning = vcm.vcm_tune_cell_size(scene, [q], cell_min=32.0, cell_max=256.0, reps=1)
-        cell = tuning["best_cell"]
+    # index autotuner (untimed set-up): the fastest column width for this map,
+    # reported; the timed steps use it with --cell -1, else the width given
+    tuning = vcm.vcm_tune_cell_size(scene, [q], cell_min=32.0, cell_max=256.0, reps=1)
+    cell = tuning["best_cell"] if args.cell < 0 else args.cell
     t0 = time.perf_counter()
     idx = vcm.vcm_build_index(scene, cell_size=cell)
     info = idx.info()
@@ -313,36 +464,59 @@ def main():
     vps = n_vp * args.steps / wall
     rays_ps = st["rays"] * args.steps / wall
 
-    ops = (OPS_PER_BOX_TEST * st["box_tests"] + OPS_PER_COLUMN * st["columns"]
-           + OPS_PER_RECORD * st["records"] + OPS_PER_NARROW_TEST * st["narrow_tests"])
-    achieved = ops / (kernel_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS,
+    # the timed map, for the comparison with the oracle below
+    gmap = {"bin": bufs[0].cpu().numpy(), "c": bufs[1].cpu().numpy(),
+            "count": bufs[2].cpu().numpy().view(np.uint16)}
+
+    rl = roofline_of(st, kernel_ms)
+    hw = None
+    if profile_valid(args.workload, info["cell_size"]):
+        valu = PROFILE_VALU[args.mode]
+        hw = {"valu_issue_per_cu_clock": valu / (CUS * kernel_ms * 1e-3 * CLOCK),
+              "source": "SQ_INSTS_VALU of the committed profile (same kernel sources)"}
+    roofline = {"bound": "alu", "achieved": rl["achieved"], "peak": PEAK_LANE_OPS / 1e12,
+                "unit": "Tlane-op/s", "frac": rl["frac"],
                 "traffic": measured_traffic(args.workload, args.mode, info["cell_size"]),
                 "kernel": "k_brute", "kernel_ms": kernel_ms,
+                "work": "20 lane-ops per float32 slab test + 12 per corridor column, per launch",
+                "lane_ops_per_launch": rl["lane_ops_per_launch"],
+                "with_culling": rl["with_culling"], "hardware": hw,
                 "box_tests_per_launch": st["box_tests"], "columns_per_launch": st["columns"],
                 "rechecks_per_launch": st["rechecks"],
                 "records_per_launch": st["records"], "narrow_tests_per_launch": st["narrow_tests"],
                 "slot_tests_per_launch": st.get("slot_tests"),
+                "open_lanes_per_slot_test": st["box_tests"] / max(1, st["slot_tests"]),
                 "inside_box_viewpoints": st.get("inside_box"),
                 "hbm_bytes_algorithmic": 7 * n_vp,
                 "hbm_frac": 7 * n_vp / (kernel_ms * 1e-3) / PEAK_HBM}
 
     extra = {}
     if not args.no_extra:
-        # FULL-mode (the paper's complete-visibility rule) throughput beside it.
+        # the other mode (FULL: the paper's complete-visibility rule) beside it,
+        # with its own useful-work fraction
         qf = scenes.Query(q.target, q.grid, scenes.Params(**{**q.params.__dict__, "mode":
                                                               scenes.FULL if mode == scenes.FRACTION
                                                               else scenes.FRACTION}))
+        st2 = vcm.vcm_compute(idx, qf, *bufs, stats=True)
         w2, k2 = timed_steps(vcm, idx, qf, bufs, max(2, args.steps // 2), 1)
+        rl2 = roofline_of(st2, float(np.mean(k2)))
         extra["other_mode"] = {"mode": "full" if mode == scenes.FRACTION else "fraction",
                                "viewpoints_per_s": n_vp * max(2, args.steps // 2) / w2,
-                               "kernel_ms": float(np.mean(k2))}
+                               "kernel_ms": float(np.mean(k2)), "roofline_frac": rl2["frac"],
+                               "roofline_frac_with_culling": rl2["with_culling"]["frac"],
+                               "box_tests_per_launch": st2["box_tests"], "columns_per_launch": st2["columns"]}
 
     if not (args.no_pruned or args.no_extra) and args.workload == "cube":
         extra["pruned"] = bench_pruned(vcm, idx, q)
-        print("pruned: " + ", ".join(f"{k} {v['ms']:.2f} ms" for k, v in extra["pruned"]["methods"].items()),
-              file=sys.stderr, flush=True)
+        for mname, leg in extra["pruned"].items():
+            print(f"pruned ({mname}): brute {leg['brute_ms']:.2f} ms, " +
+                  ", ".join(f"{k} {v['ms']:.2f} ms" for k, v in leg["methods"].items()),
+                  file=sys.stderr, flush=True)
+    if not (args.no_index or args.no_extra):
+        extra["index_build"] = bench_index()
+    if not (args.no_sweeps or args.no_extra):
+        extra["sweeps"] = bench_sweeps()
+        print("sweeps: done", file=sys.stderr, flush=True)
     if not (args.no_batch or args.no_extra):
         extra["batch"] = bench_batch()
         print(f"batch: {extra['batch']['speedup_vs_sequential']:.2f}x sequential", file=sys.stderr,
@@ -351,6 +525,7 @@ def main():
         extra["serving"] = bench_serve(args.serve_requests)
 
     cpu = None
+    agreement = None
     if not args.no_cpu:
         import oracle
         vp = scenes.viewpoint_sample(q.grid, args.cpu_sample, 12345)
@@ -361,13 +536,15 @@ def main():
                "sample": f"{len(vp)} seeded uniform-random viewpoints of the same grid and mode, "
                          f"single thread, {dt:.1f} s",
                "rays_per_s": float(o["nlive"][o["infov"] > 0].astype(np.int64).sum()) / dt}
-        # the same oracle split over the host's cores (reported beside it)
-        ncores = min(16, len(os.sched_getaffinity(0)))
+        # the timed map's error against the float64 oracle on that sample
+        agreement = oracle_agreement({k: v[vp] for k, v in gmap.items()}, o, q.params.n_bins)
+        # the same oracle split over all the host's cores (reported beside it)
+        ncores = len(os.sched_getaffinity(0))
         t0 = time.perf_counter()
         oracle.vcm_eval(scene, q, vp, nthreads=ncores)
         dt_all = time.perf_counter() - t0
         extra["cpu_baseline_all_cores"] = {"value": len(vp) / dt_all, "unit": "viewpoints/s",
-                                           "cores": ncores, "kind": "oracle",
+                                           "cores": ncores, "nproc": os.cpu_count(), "kind": "oracle",
                                            "sample": f"the same {len(vp)} viewpoints, {ncores} threads"}
 
     line = {
@@ -396,6 +573,7 @@ def main():
                   "cell_tuning": tuning},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "oracle_agreement": agreement,
         **extra,
     }
     print(json.dumps(line), flush=True)

@@ -235,12 +235,16 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
                         else tight = tight && s2 <= 0.0f;
                         m0 = fmaxf(0.0f, m0 - kLambdaMargin);
                         m1 = fminf(1.0f, m1 + kLambdaMargin);
-                        tight = tight && m0 <= m1;
-                        tight = tight && R.hi[BX] >= fminf(qb + m0 * vb0, qb + m1 * vb0) - kWalkMargin &&
-                                R.lo[BX] <= fmaxf(qb + m0 * vb1, qb + m1 * vb1) + kWalkMargin;
-                        if (DIM == 3)
-                            tight = tight && R.hi[2] >= fminf(qz + m0 * wz0, qz + m1 * wz0) - kWalkMargin &&
-                                    R.lo[2] <= fmaxf(qz + m0 * wz1, qz + m1 * wz1) + kWalkMargin;
+                        // every condition evaluated (no divergent branches)
+                        const bool e0 = m0 <= m1;
+                        const bool e1 = R.hi[BX] >= fminf(qb + m0 * vb0, qb + m1 * vb0) - kWalkMargin;
+                        const bool e2 = R.lo[BX] <= fmaxf(qb + m0 * vb1, qb + m1 * vb1) + kWalkMargin;
+                        bool e3 = true, e4 = true;
+                        if (DIM == 3) {
+                            e3 = R.hi[2] >= fminf(qz + m0 * wz0, qz + m1 * wz0) - kWalkMargin;
+                            e4 = R.lo[2] <= fmaxf(qz + m0 * wz1, qz + m1 * wz1) + kWalkMargin;
+                        }
+                        tight = tight & e0 & e1 & e2 & e3 & e4;
                         cand &= __ballot(tight);
                     }
                     if (cand) {
@@ -323,6 +327,42 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
     }
 }
 
+// Is q inside (or on) an obstacle?  Boxes of the index frame have no
+// negative coordinate, so the scan of q's column compares ordered bit
+// patterns, 64 records at a time; the column's list ends with a sentinel
+// (top -inf, lower corner +inf).
+template <int DIM, bool STATS>
+__device__ __attribute__((always_inline)) inline bool inside_obstacle(const DevIndex &X, cptr_i32 col_start,
+                                                                      cptr_rec recs, const float *q,
+                                                                      WaveStats &ws) {
+    const int lane = threadIdx.x & 63;
+    if (!(q[0] >= 0.0f && q[1] >= 0.0f && q[2] >= 0.0f)) return false;
+    const int cx = static_cast<int>(floorf(q[0] * X.inv_cs));
+    const int cy = static_cast<int>(floorf(q[1] * X.inv_cs));
+    if (!(cx < X.nx && cy < X.ny)) return false;
+    const unsigned u0 = __builtin_amdgcn_readfirstlane(ord(q[0]));
+    const unsigned u1 = __builtin_amdgcn_readfirstlane(ord(q[1]));
+    const unsigned u2 = __builtin_amdgcn_readfirstlane(ord(q[2]));
+    const int cb = col_start[cx + X.nx * cy], ce = col_start[cx + X.nx * cy + 1] - 1;
+    for (int base = cb;; base += 64) {
+        const BoxRec R = recs[min(base + lane, ce)];
+        // not lower than q (the list is sorted by decreasing top)
+        const bool above = static_cast<int>(__float_as_uint(R.hi[2]) - u2) >= 0;
+        const int out = static_cast<int>(u0 - __float_as_uint(R.lo[0])) |
+                        static_cast<int>(__float_as_uint(R.hi[0]) - u0) |
+                        static_cast<int>(u1 - __float_as_uint(R.lo[1])) |
+                        static_cast<int>(__float_as_uint(R.hi[1]) - u1) |
+                        (DIM == 3 ? static_cast<int>(u2 - __float_as_uint(R.lo[2])) : 0);
+        const unsigned long long below = __ballot(!above);
+        if (STATS) ws.recs += __popcll(__ballot(above)) + (below ? 1 : 0);
+        if (__ballot(above && out >= 0)) {
+            if (STATS) ++ws.inside;
+            return true;
+        }
+        if (below) return false;
+    }
+}
+
 // Visibility of the live samples from q for one wavefront.  Returns the
 // number of unblocked live samples (FULL mode: exact only when it equals N).
 //
@@ -341,49 +381,22 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
     const DevIndex &X = A.idx;
     const int lane = threadIdx.x & 63;
 
-    // ---- a viewpoint inside (or on) an obstacle sees nothing.  Boxes of the
-    // index frame have no negative coordinate, so the scan of q's column
-    // compares ordered bit patterns, 64 records at a time; the column's list
-    // ends with a sentinel (top -inf, lower corner +inf).
-    if (q[0] >= 0.0f && q[1] >= 0.0f && q[2] >= 0.0f) {
-        const int cx = static_cast<int>(floorf(q[0] * X.inv_cs));
-        const int cy = static_cast<int>(floorf(q[1] * X.inv_cs));
-        if (cx < X.nx && cy < X.ny) {
-            const unsigned u0 = __builtin_amdgcn_readfirstlane(ord(q[0]));
-            const unsigned u1 = __builtin_amdgcn_readfirstlane(ord(q[1]));
-            const unsigned u2 = __builtin_amdgcn_readfirstlane(ord(q[2]));
-            const int cb = col_start[cx + X.nx * cy], ce = col_start[cx + X.nx * cy + 1] - 1;
-            for (int base = cb;; base += 64) {
-                const BoxRec R = recs[min(base + lane, ce)];
-                // not lower than q (the list is sorted by decreasing top)
-                const bool above = static_cast<int>(__float_as_uint(R.hi[2]) - u2) >= 0;
-                const int out = static_cast<int>(u0 - __float_as_uint(R.lo[0])) |
-                                static_cast<int>(__float_as_uint(R.hi[0]) - u0) |
-                                static_cast<int>(u1 - __float_as_uint(R.lo[1])) |
-                                static_cast<int>(__float_as_uint(R.hi[1]) - u1) |
-                                (DIM == 3 ? static_cast<int>(u2 - __float_as_uint(R.lo[2])) : 0);
-                const unsigned long long below = __ballot(!above);
-                if (STATS) ws.recs += __popcll(__ballot(above)) + (below ? 1 : 0);
-                if (__ballot(above && out >= 0)) {
-                    if (STATS) ++ws.inside;
-                    return 0;
-                }
-                if (below) break;
-            }
-        }
-    }
+    // FULL mode: the box that blocked the previous viewpoint of this work
+    // item usually blocks this one too, and one blocked ray settles the
+    // viewpoint; each slot is tested against it as soon as it is set up, so
+    // a viewpoint settled by an early slot sets up no more rays.  A viewpoint
+    // inside an obstacle sees nothing, which is also what a blocked ray
+    // gives in FULL mode, so with a cached blocker the column scan for it
+    // waits until the blocker has failed to settle the viewpoint.
+    const bool cached = MODE == VCM_FULL && blk >= 0;
+    if (!cached && inside_obstacle<DIM, STATS>(X, col_start, recs, q, ws)) return 0;
 
     // ---- rays: slot j, lane l holds live sample j*64 + l
     float iv[NS][3];
     int sidx[NS];
     unsigned long long open[NS];
     unsigned long long zmask[NS];  // rays with a zero direction component
-    // FULL mode: the box that blocked the previous viewpoint of this work
-    // item usually blocks this one too, and one blocked ray settles the
-    // viewpoint; each slot is tested against it as soon as it is set up, so
-    // a viewpoint settled by an early slot sets up no more rays.
     float bl[3] = {0.0f, 0.0f, 0.0f}, bh[3] = {0.0f, 0.0f, 0.0f};
-    const bool cached = MODE == VCM_FULL && blk >= 0;
     if (cached) {
         const BoxRec B = recs[blk];
 #pragma unroll
@@ -405,6 +418,7 @@ __device__ __attribute__((always_inline)) inline int trace_viewpoint(
                                                     n_disagree) != 0)
             return 0;
     }
+    if (cached && inside_obstacle<DIM, STATS>(X, col_start, recs, q, ws)) return 0;
 
     // ---- corridor walk along the major horizontal axis of q - c
     if (fabsf(T.c[0] - q[0]) >= fabsf(T.c[1] - q[1]))
