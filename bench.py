@@ -37,11 +37,11 @@ PEAK_HBM = 8.0e12
 # FETCH_SIZE / WRITE_SIZE summary (copy-kernel calibrated), valid only for the
 # kernel sources it was taken on.
 PROFILE = os.path.join(ROOT, "profiles", "k_brute_city20k_cube_fraction.md")
-TRAFFIC_BYTES = 87600525
+TRAFFIC_BYTES = 82427745
 TRAFFIC_CELL = 128.0
 KERNEL_SOURCES = ("brute.hip", "trace_common.h", "index.hip", "vcm_internal.h")
 # Issue counters of the same profile (per launch), valid under the same hash.
-PROFILE_VALU = {"fraction": 2.740e9, "full": 6.827e8}
+PROFILE_VALU = {"fraction": 2.792e9, "full": 6.053e8}
 CUS, CLOCK = 256, 2.4e9
 
 
@@ -500,7 +500,11 @@ def main():
         st2 = vcm.vcm_compute(idx, qf, *bufs, stats=True)
         w2, k2 = timed_steps(vcm, idx, qf, bufs, max(2, args.steps // 2), 1)
         rl2 = roofline_of(st2, float(np.mean(k2)))
-        extra["other_mode"] = {"mode": "full" if mode == scenes.FRACTION else "fraction",
+        other = "full" if mode == scenes.FRACTION else "fraction"
+        hw2 = None
+        if profile_valid(args.workload, info["cell_size"]):
+            hw2 = PROFILE_VALU[other] / (CUS * float(np.mean(k2)) * 1e-3 * CLOCK)
+        extra["other_mode"] = {"mode": other, "valu_issue_per_cu_clock": hw2,
                                "viewpoints_per_s": n_vp * max(2, args.steps // 2) / w2,
                                "kernel_ms": float(np.mean(k2)), "roofline_frac": rl2["frac"],
                                "roofline_frac_with_culling": rl2["with_culling"]["frac"],
