@@ -227,8 +227,10 @@ typedef struct {
     uint64_t blocks;         /* visible-region blocks classified (Sec.
                                 III-C-1), over every level of the tree      */
     uint64_t blocks_decided; /* of which decided as a whole                  */
-    uint64_t leaves;         /* undecided smallest blocks, traced at their
-                                representative viewpoint                    */
+    uint64_t leaves;         /* theta > 1: undecided smallest blocks, traced
+                                at their representative viewpoint; theta = 1:
+                                viewpoints the blocks left undecided, traced
+                                one by one                                  */
 } vcm_stats;
 
 /* Results: caller-owned buffers of grid.n[0]*n[1]*n[2] entries.

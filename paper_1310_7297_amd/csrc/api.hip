@@ -261,7 +261,11 @@ WsLayout query_workspace(const GridDesc &g, int dim, int method, int theta, bool
         w.plan = block_plan(g, dim, theta);
         w.gate = off;
         off += ws_align(sizeof(uint32_t) * static_cast<size_t>(g.count));
+        // the block lists launch_blocks reads and writes: the inputs of the
+        // classified levels below the root, and (theta > 1) the undecided
+        // smallest blocks
         for (int l = 1; l <= w.plan.levels; ++l) {
+            if (!(l < w.plan.classified || (w.plan.leaf > 1 && l == w.plan.leaf_list))) continue;
             w.lists[l] = off;
             off += ws_align(sizeof(uint32_t) * static_cast<size_t>(w.plan.count[std::min(l, w.plan.levels - 1)]));
         }
@@ -287,16 +291,16 @@ vcm_status run_query(const Index &ix, const TargetDesc &t, const GridDesc &g, co
     if (g.count <= 0) return VCM_OK;
     if (g.count >= (int64_t(1) << 32))
         return set_error(VCM_E_INVALID, "pruned methods take grids of fewer than 2^32 viewpoints");
-    // pruned: the visible-region blocks, the representatives of the undecided
-    // smallest ones, then the cell colours of every viewpoint
+    // pruned: the visible-region blocks, the viewpoints (or, theta > 1, the
+    // representatives of the smallest blocks) they leave undecided, then the
+    // cell colours of every viewpoint
     uint32_t *gate = reinterpret_cast<uint32_t *>(ws + w.gate);
     uint32_t *lists[kMaxBlockLevels + 1] = {};
     for (int l = 1; l <= w.plan.levels; ++l) lists[l] = reinterpret_cast<uint32_t *>(ws + w.lists[l]);
     unsigned *ctr = reinterpret_cast<unsigned *>(ws + w.ctr);
+    if (w.plan.leaf == 1) launch_gate_clear(gate, g.count, s);
     vcm_status st = launch_blocks(ix, t, g, p, w.plan, gate, lists, ctr, s, stats);
-    const int lv = w.plan.leaf_list;
-    if (st == VCM_OK)
-        st = launch_leaves(ix, t, g, p, w.plan, gate, lists[lv], ctr + lv, ctr + 2 * w.plan.levels + 1, s, stats);
+    if (st == VCM_OK) st = launch_undecided(ix, t, g, p, w.plan, gate, lists, ctr, counter, s, stats);
     if (st == VCM_OK)
         st = launch_pruned(ix, t, g, p, method, gate, r, s, stats ? &stats->t_fallbacks : nullptr,
                            w.n_sums ? reinterpret_cast<double *>(ws + w.sums) : nullptr);

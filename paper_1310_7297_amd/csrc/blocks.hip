@@ -418,7 +418,7 @@ __global__ __launch_bounds__(256) void k_blocks(BlockLevel B, const int32_t *col
                 B.gate[i + static_cast<int64_t>(G.n[0]) * (j + static_cast<int64_t>(G.n[1]) * k)] = word;
             }
         } else if (B.child == 0) {
-            if (lane == 0) B.out_list[atomicAdd(B.out_count, 1u)] = b;
+            if (lane == 0 && B.out_list) B.out_list[atomicAdd(B.out_count, 1u)] = b;
         } else {
             // the sub-blocks of edge B.child that hold viewpoints (at most 64:
             // the octants, or the viewpoints of a block of edge 4), lane t
@@ -464,8 +464,7 @@ void dispatch_blocks(int ns, F &&f) {
 
 }  // namespace
 
-// An undecided block hands down at most 64 sub-blocks, one per lane.
-static_assert(kMinClassifiedSide >= 2 && kMinClassifiedSide <= 4, "sub-blocks of a block must fit one wavefront");
+static_assert(kMinClassifiedSide >= 2, "blocks of one viewpoint are traced, not classified");
 static_assert(kRootBlockSide >= kMinClassifiedSide, "the root level is classified");
 
 int block_leaf_side(int theta) {
@@ -514,15 +513,17 @@ vcm_status launch_blocks(const Index &ix, const TargetDesc &t, const GridDesc &g
         B.in_count = l == 0 ? nullptr : ctr + l;
         B.n_all = static_cast<uint32_t>(bp.count[0]);
         const bool last = l == bp.classified - 1;
-        B.out_list = last ? lists[bp.leaf_list] : lists[l + 1];
+        // theta = 1: the last classified level lists nothing (the ray kernel
+        // traces every viewpoint whose gate is still undecided)
+        B.out_list = last ? (bp.leaf > 1 ? lists[bp.leaf_list] : nullptr) : lists[l + 1];
         B.out_count = last ? ctr + bp.leaf_list : ctr + l + 1;
         B.claim = ctr + bp.levels + 1 + l;
         B.stats = stats;
         B.side = bp.side[l];
         // sub-blocks of undecided blocks: the next level's; at the last
-        // classified level, none (theta > 1: the block is a smallest block)
-        // or its viewpoints (theta = 1)
-        B.child = !last ? bp.side[l] / 2 : (bp.leaf > 1 ? 0 : 1);
+        // classified level, none (theta > 1: the block is a smallest block,
+        // listed itself; theta = 1: not listed)
+        B.child = !last ? bp.side[l] / 2 : 0;
         const int cs = std::max(1, B.child);
         for (int k = 0; k < 3; ++k) {
             B.nb[k] = k < ix.dim ? (g.n[k] + B.side - 1) / B.side : 1;

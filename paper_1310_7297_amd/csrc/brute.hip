@@ -25,7 +25,8 @@ namespace vcm {
 namespace {
 
 struct WaveStats {
-    unsigned long long tests = 0, slots = 0, rechecks = 0, cols = 0, rays = 0, inside = 0, recs = 0, narrow = 0;
+    unsigned long long tests = 0, slots = 0, rechecks = 0, cols = 0, rays = 0, inside = 0, recs = 0, narrow = 0,
+                       filled = 0;
 };
 
 // FRACTION-mode compaction buffer of a wavefront, one entry per ray: with up
@@ -499,7 +500,14 @@ __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &
     int o_cnt = 0, o_n = 0;
     bool o_fov = false;
     int blk = -1;  // record of the last blocking box (FULL mode)
+    // fill mode: lane t holds the gate word the block tree left for
+    // viewpoint t; only undecided viewpoints are traced and written
+    uint32_t pre = kGateUndecided;
+    if (A.fill && lane < nv) pre = A.gate[v0 + lane];
     for (int t = 0; t < nv; ++t) {
+        if (A.fill && static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(pre), t)) != kGateUndecided)
+            continue;
+        if (STATS && A.fill) ++ws.filled;
         // grid index; in gate mode the launch grid is the block grid and
         // each block is represented by its lowest-index centre viewpoint
         int ii[3] = {x0 + t, jj, kk};
@@ -551,8 +559,9 @@ __device__ __attribute__((always_inline)) inline void run_item(const BruteArgs &
     }
     if (lane < nv) {
         if (A.gate) {
-            A.gate[v0 + lane] = static_cast<uint32_t>(o_cnt) | (static_cast<uint32_t>(o_n) << 10) |
-                                (o_fov ? (1u << 20) : 0u);
+            if (pre == kGateUndecided)
+                A.gate[v0 + lane] = static_cast<uint32_t>(o_cnt) | (static_cast<uint32_t>(o_n) << 10) |
+                                    (o_fov ? (1u << 20) : 0u);
         } else {
             // measure and bin, one lane per viewpoint of the item (the lane
             // computes its viewpoint's position exactly as the walk did)
@@ -584,6 +593,7 @@ __device__ inline void flush_stats(DevStats *st, const WaveStats &ws, unsigned l
         atomicAdd(&st->inside_box, ws.inside);
         atomicAdd(&st->records, ws.recs);
         atomicAdd(&st->narrow_tests, ws.narrow);
+        if (ws.filled) atomicAdd(&st->leaves, ws.filled);
     }
     if (n_disagree) atomicAdd(&st->fp32_disagree, n_disagree);  // per lane
 }
@@ -681,6 +691,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE
 // viewpoint of the block -- traced like any viewpoint, for all the
 // viewpoints it holds.  One wavefront per block.
 constexpr int kLeafRun = 8;
+
+// Every word of p set to v (grid-stride).
+__global__ void k_fill_words(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
 
 struct LeafArgs {
     const uint32_t *list;   // blocks (index in the leaf level's block grid)
@@ -926,13 +943,28 @@ vcm_status launch_leaves(const Index &ix, const TargetDesc &t, const GridDesc &g
     return VCM_OK;
 }
 
+void launch_gate_clear(uint32_t *gate, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_words, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, gate, n, kGateUndecided);
+}
+
+vcm_status launch_undecided(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
+                            const BlockPlan &bp, uint32_t *gate, uint32_t *const *lists, unsigned *ctr,
+                            unsigned *counter, hipStream_t s, DevStats *stats) {
+    if (bp.leaf == 1) return launch_brute(ix, t, g, p, vcm_result{}, s, stats, gate, 1, Tuning{}, counter, 1);
+    const int lv = bp.leaf_list;
+    return launch_leaves(ix, t, g, p, bp, gate, lists[lv], ctr + lv, ctr + 2 * bp.levels + 1, s, stats);
+}
+
 vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_in,
                         const ParamDesc &p, const vcm_result &r, hipStream_t stream,
                         DevStats *stats, uint32_t *gate, int theta, const Tuning &tune,
-                        unsigned *counter) {
+                        unsigned *counter, int fill) {
     if (g_in.count <= 0) return VCM_OK;
     BruteArgs a = make_brute_args(ix, t, g_in, p, r, gate, theta, chunk_for(tune, p.mode));
     a.stats = stats;
+    a.fill = gate && theta == 1 && fill ? 1 : 0;
     const int ns = slots_for(t);
     if (ns < 1 || ns > kMaxSlots) return set_error(VCM_E_INVALID, "too many target samples");
     a.counter = counter;

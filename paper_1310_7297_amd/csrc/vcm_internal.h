@@ -142,8 +142,13 @@ struct BruteArgs {
     int32_t k_begin;    // first z layer of this launch
     uint32_t n_items;   // work items in this launch
     int32_t chunk;      // viewpoints of one grid row per work item (1..64)
-    int32_t pad;
+    int32_t fill;       // gate mode, theta = 1: trace only the viewpoints whose
+                        // gate word is kGateUndecided (the block tree decided
+                        // the others)
 };
+
+// Gate word of a viewpoint the visible-region blocks left undecided.
+constexpr uint32_t kGateUndecided = 0xffffffffu;
 
 // A launch over the work items of many queries.
 struct BatchArgs {
@@ -215,7 +220,7 @@ vcm_status prepare_query(const Index &ix, const vcm_query &q, TargetDesc *t, Gri
 vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g,
                         const ParamDesc &p, const vcm_result &r, hipStream_t stream,
                         DevStats *stats, uint32_t *gate, int theta, const Tuning &tune,
-                        unsigned *counter);
+                        unsigned *counter, int fill = 0);
 
 // Pieces of a batched launch.
 int device_cus(int device);
@@ -237,12 +242,13 @@ vcm_status launch_brute_batch(const Index &ix, bool fp64, int mode, int ns, cons
 #define VCM_ROOT_BLOCK_SIDE 8
 #endif
 #ifndef VCM_MIN_CLASSIFIED_SIDE
-#define VCM_MIN_CLASSIFIED_SIDE 4
+#define VCM_MIN_CLASSIFIED_SIDE 8
 #endif
 constexpr int kRootBlockSide = VCM_ROOT_BLOCK_SIDE;
-// With theta = 1 every viewpoint the tree leaves undecided is traced exactly,
-// so blocks below this side are not classified: tracing their viewpoints
-// costs less than classifying them (measured).
+// With theta = 1 every viewpoint the tree leaves undecided is traced exactly
+// (by the ray kernel over the grid, skipping decided viewpoints), so blocks
+// below this side are not classified: tracing their viewpoints costs less
+// than classifying them (measured).
 constexpr int kMinClassifiedSide = VCM_MIN_CLASSIFIED_SIDE;
 constexpr int kMaxBlockLevels = 16;
 struct BlockPlan {
@@ -269,6 +275,17 @@ vcm_status launch_blocks(const Index &ix, const TargetDesc &t, const GridDesc &g
 vcm_status launch_leaves(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
                          const BlockPlan &bp, uint32_t *gate, const uint32_t *list, const unsigned *count,
                          unsigned *claim, hipStream_t s, DevStats *stats);
+// Before launch_blocks with theta = 1: every gate word set to kGateUndecided.
+void launch_gate_clear(uint32_t *gate, int64_t n, hipStream_t s);
+// After launch_blocks: the gates of the viewpoints the tree left undecided.
+// theta = 1: the ray kernel over the whole grid, tracing only the viewpoints
+// whose gate word is still kGateUndecided (work items of consecutive
+// viewpoints keep the ray kernel's blocker cache); theta > 1: launch_leaves
+// over the undecided smallest blocks.  `counter`: the work-item counters of
+// launch_brute.
+vcm_status launch_undecided(const Index &ix, const TargetDesc &t, const GridDesc &g, const ParamDesc &p,
+                            const BlockPlan &bp, uint32_t *gate, uint32_t *const *lists, unsigned *ctr,
+                            unsigned *counter, hipStream_t s, DevStats *stats);
 
 // Pruned colouring (E / M / T) of every viewpoint from its gate word.
 // With `sums` non-null (pruned_sum_blocks(g) x kPrunedSums doubles), each

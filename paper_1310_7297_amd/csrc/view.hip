@@ -133,10 +133,11 @@ vcm_status vcm_view_create(const vcm_index *index, const vcm_query *query, void 
             uint32_t *lists[kMaxBlockLevels + 1] = {};
             for (int l = 1; l <= w.plan.levels; ++l) lists[l] = reinterpret_cast<uint32_t *>(ws + w.lists[l]);
             unsigned *ctr = reinterpret_cast<unsigned *>(ws + w.ctr);
+            if (w.plan.leaf == 1) launch_gate_clear(v->gate, v->g.count, s);
             st = launch_blocks(ix, v->t, v->g, v->p, w.plan, v->gate, lists, ctr, s, nullptr);
             if (st == VCM_OK)
-                st = launch_leaves(ix, v->t, v->g, v->p, w.plan, v->gate, lists[w.plan.leaf_list],
-                                   ctr + w.plan.leaf_list, ctr + 2 * w.plan.levels + 1, s, nullptr);
+                st = launch_undecided(ix, v->t, v->g, v->p, w.plan, v->gate, lists, ctr,
+                                      reinterpret_cast<unsigned *>(ws + w.counter), s, nullptr);
         }
     }
     const hipError_t e = hipStreamSynchronize(s);
