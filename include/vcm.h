@@ -225,10 +225,14 @@ typedef struct {
                                 gate) times the area (2-D) or volume (3-D)
                                 of one lattice cell                         */
     uint64_t blocks;         /* visible-region blocks classified (Sec.
-                                III-C-1), over every level of the tree      */
+                                III-C-1): those of edge 8 and more; below
+                                that, tracing replaces classifying (the map
+                                is the same)                                */
     uint64_t blocks_decided; /* of which decided as a whole                  */
-    uint64_t leaves;         /* theta > 1: undecided smallest blocks, traced
-                                at their representative viewpoint; theta = 1:
+    uint64_t leaves;         /* theta > 1: smallest blocks (edge theta,
+                                rounded down to a power of two) of the
+                                undecided classified blocks, traced at their
+                                representative viewpoint; theta = 1:
                                 viewpoints the blocks left undecided, traced
                                 one by one                                  */
 } vcm_stats;
@@ -266,7 +270,7 @@ vcm_status vcm_compute(const vcm_index *index, const vcm_query *query,
  * on that device until the process ends.  A query that needs more scratch
  * than that fails with VCM_E_INVALID before any device work: a brute-force
  * map needs 2 KiB, a pruned map about 4 bytes per viewpoint more (a gate
- * word per viewpoint and the block lists of every level of the hierarchy),
+ * word per viewpoint and the lists of classified and smallest blocks),
  * so grids of up to about 16 million viewpoints.  Every call on
  * one device shares the array, so calls that overlap on a device (other
  * streams, other threads) race; the caller must order them.  Enqueues on
@@ -359,7 +363,7 @@ vcm_status vcm_tune_cell_size(const vcm_obstacles *obstacles, const vcm_query *q
  * thread.  Admission is by device memory: a request's footprint is its result
  * buffers (1 B bin + 4 B colour + 2 B count per viewpoint, for the buffers
  * given), its work record and, for the pruned methods, the workspace of the
- * block hierarchy (4 B per viewpoint and 4 B per block of every level);
+ * block hierarchy (4 B per viewpoint and 4 B per listed block);
  * a request is admitted while the footprints of all unfinished requests fit
  * in mem_budget_bytes.  One engine thread batches the admitted requests as
  * they arrive: whenever one of max_inflight launch slots (streams) is free it

@@ -21,6 +21,14 @@
 //     one of its viewpoints; an undecided one is split into its octants, or,
 //     at the smallest size, listed for the ray kernel, which traces its
 //     representative viewpoint (k_leaves in brute.hip).
+// A decided block's gate is the traced gate of each of its viewpoints (the
+// tests above are exact), so a decided block's sub-blocks would be decided
+// alike.  The map is therefore the same when the levels between blocks of 8
+// and the smallest blocks are not classified: the undecided blocks of 8 list
+// their smallest sub-blocks straight away, and each of those takes its
+// representative's traced gate, which a classification could only confirm.
+// Tracing a representative costs less than classifying a block (measured),
+// so only blocks of edge 8 and more are classified.
 // The candidate obstacles are those of the columns crossed by the convex hull
 // of the block and the target's box, walked slab by slab along the major
 // horizontal axis as for a single viewpoint.
@@ -421,8 +429,8 @@ __global__ __launch_bounds__(256) void k_blocks(BlockLevel B, const int32_t *col
             if (lane == 0 && B.out_list) B.out_list[atomicAdd(B.out_count, 1u)] = b;
         } else {
             // the sub-blocks of edge B.child that hold viewpoints (at most 64:
-            // the octants, or the viewpoints of a block of edge 4), lane t
-            // taking sub-block t
+            // the octants, or the smallest blocks of a block at most 4 of
+            // them wide), lane t taking sub-block t
             const int r = B.side / B.child;
             const int tot = DIM == 3 ? r * r * r : r * r;
             int c[3] = {0, 0, 0};
@@ -483,12 +491,16 @@ BlockPlan block_plan(const GridDesc &g, int dim, int theta) {
         for (int k = 0; k < 3; ++k) n *= k < dim ? (g.n[k] + s - 1) / s : 1;
         bp.side[bp.levels] = s;
         bp.count[bp.levels] = n;
-        if (bp.leaf > 1 || s >= kMinClassifiedSide) bp.classified = bp.levels + 1;
+        // classified: blocks of edge kMinClassifiedSide and more, and (theta
+        // > 1) those more than 4 smallest blocks wide, whose smallest blocks
+        // would not fit one wavefront's list step
+        if (s >= kMinClassifiedSide || (bp.leaf > 1 && s > 4 * bp.leaf)) bp.classified = bp.levels + 1;
         ++bp.levels;
     }
     if (bp.classified == 0) bp.classified = 1;
-    // the ray kernel's list: the undecided smallest blocks; with theta = 1,
-    // the viewpoints of the undecided blocks of the last classified level
+    // the ray kernel's list: theta > 1, the smallest blocks of the undecided
+    // blocks of the last classified level (its representatives are traced);
+    // theta = 1, none (the viewpoints of those blocks are traced)
     bp.leaf_list = bp.leaf > 1 ? bp.levels : bp.levels - 1;
     return bp;
 }
@@ -521,9 +533,14 @@ vcm_status launch_blocks(const Index &ix, const TargetDesc &t, const GridDesc &g
         B.stats = stats;
         B.side = bp.side[l];
         // sub-blocks of undecided blocks: the next level's; at the last
-        // classified level, none (theta > 1: the block is a smallest block,
-        // listed itself; theta = 1: not listed)
-        B.child = !last ? bp.side[l] / 2 : 0;
+        // classified level, theta > 1: its smallest blocks (none when it is
+        // the smallest level: the block is listed itself); theta = 1: not
+        // listed
+        B.child = !last ? bp.side[l] / 2 : (bp.leaf > 1 && bp.leaf < bp.side[l] ? bp.leaf : 0);
+        if (B.child > 0) {
+            const int r = bp.side[l] / B.child;
+            if ((ix.dim == 3 ? r * r * r : r * r) > 64) return set_error(VCM_E_INTERNAL, "block plan: too many sub-blocks");
+        }
         const int cs = std::max(1, B.child);
         for (int k = 0; k < 3; ++k) {
             B.nb[k] = k < ix.dim ? (g.n[k] + B.side - 1) / B.side : 1;

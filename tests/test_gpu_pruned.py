@@ -58,9 +58,12 @@ def test_plain2d_full_map(method, mode, theta):
 @pytest.mark.parametrize("theta", [1, 2, 4])
 @pytest.mark.parametrize("mode", [FULL, FRACTION])
 def test_small_3d_full_map(method, kind, theta, mode):
-    """Whole maps against the oracle, the visible-region blocks included:
-    the same blocks are decided, the undecided smallest ones take their
-    representative's gate."""
+    """Whole maps against the oracle, the visible-region blocks included.
+    The oracle classifies every level of the tree down to the smallest
+    blocks; the library classifies blocks of 8 and traces the
+    representatives of the smallest blocks of the undecided ones.  The maps
+    are the same, since a decided block's gate is each of its viewpoints'
+    traced gate."""
     if kind == CUBE:
         t = Target(CUBE, (64.0, 64.0, 4.0), (8.0, 0.0), samples_u=4, samples_v=4)
     else:
@@ -78,9 +81,11 @@ def test_small_3d_full_map(method, kind, theta, mode):
     st = gm["stats"]
     assert 0 < st["blocks"] and st["blocks_decided"] <= st["blocks"]
     if theta > 1:
-        # the tree is classified down to the smallest blocks; every undecided
-        # one is traced once, at its representative
-        assert st["blocks_decided"] > 0 and 0 < st["leaves"] <= st["blocks"]
+        # blocks of 8 are classified (on this 7-deep grid none is decided);
+        # the smallest blocks of each undecided one are traced once, at
+        # their representative
+        per = (8 // theta) ** 3
+        assert 0 < st["leaves"] <= (st["blocks"] - st["blocks_decided"]) * per
     else:
         # theta = 1: the viewpoints the blocks leave undecided are traced
         assert 0 < st["leaves"] <= g.count
@@ -105,6 +110,7 @@ def test_city4km_cube_sampled(method, theta):
     o = oracle.vcm_eval_pruned(scene, q, method, theta, vp, nthreads=16)
     compare_pruned(g, o, scene, q, vp, method)
     assert (o["count"] > 0).sum() >= 10
+    assert g["stats"]["blocks_decided"] > 0
 
 
 @pytest.mark.parametrize("mode", [FULL, FRACTION])

@@ -213,3 +213,7 @@ def test_pruned_gate_is_brute_force_where_decided_and_the_representative_elsewhe
     assert 0.2 < dec.mean() < 0.98
     assert np.array_equal(p["count"][dec], b["count"][dec])
     assert np.array_equal(p["count"][~dec], b["count"][reps[~dec]])
+    # hence the whole map is every smallest block's representative's gate:
+    # a decided block gives its representatives the gate it gives the block,
+    # so the map does not depend on which levels of the tree are classified
+    assert np.array_equal(p["count"], b["count"][reps])
