@@ -123,6 +123,8 @@ def parse():
     ap.add_argument("--no-pruned", action="store_true", help="skip the pruned-construction leg")
     ap.add_argument("--no-index", action="store_true", help="skip the index-build leg (100,000 boxes)")
     ap.add_argument("--no-sweeps", action="store_true", help="skip the parameter sweeps (mu, theta, FOV, obstacles)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 2-D plain and 2 km billboard maps timed beside the headline")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests per arrival rate of the serving leg (2,000 as configured)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -160,6 +162,55 @@ def timed_steps(vcm, idx, q, bufs, steps, warmup):
     wall = time.perf_counter() - t0
     kms = [e0.elapsed_time(e1) for e0, e1 in evs]
     return wall, kms
+
+
+def bench_configs(steps: int):
+    """The two smaller configurations beside the headline, brute force in both
+    modes: the 2-D plain map (1000 x 1000, 50 rectangles, segment target of
+    32 samples, 64 x 64 viewpoints, float64 throughout) and the 3-D plain map
+    (2 km city, 5,000 boxes, 10 x 5 m billboard 16 x 8, 128 x 128 x 32
+    viewpoints, float32 + exact recheck).  Returns the figures and, per map,
+    its outputs on a sample of viewpoints (all of the 2-D map), which the
+    oracle leg compares with the float64 oracle."""
+    import numpy as np
+    import torch
+    import paper_1310_7297_amd as vcm
+    from paper_1310_7297_amd import scenes
+    out, samples = {}, []
+    for name, cfg, prec, n_sample in (("plain2d_50rects", scenes.plain2d_50rects, vcm.VCM_FP64, 4096),
+                                      ("city2km_billboard", scenes.city2km_billboard, vcm.VCM_FP32_RECHECK,
+                                       16384)):
+        scene, q0 = cfg()
+        idx = vcm.vcm_build_index(scene)
+        n = q0.grid.count
+        bufs = vcm.alloc_result(n)
+        vp = scenes.viewpoint_sample(q0.grid, n_sample, 777)
+        leg = {"viewpoints": n, "boxes": scene.n, "precision": "f64" if prec == vcm.VCM_FP64 else "f32+f64recheck",
+               "cell_size": idx.info()["cell_size"]}
+        for mname, mode in (("full", scenes.FULL), ("fraction", scenes.FRACTION)):
+            q = scenes.Query(q0.target, q0.grid, scenes.Params(**{**q0.params.__dict__, "mode": mode}))
+            st = vcm.vcm_compute(idx, q, *bufs, stats=True, precision=prec)
+            vcm.vcm_compute(idx, q, *bufs, precision=prec)
+            torch.cuda.synchronize()
+            stream = torch.cuda.current_stream()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(steps)]
+            t0 = time.perf_counter()
+            for e0, e1 in evs:
+                e0.record(stream)
+                vcm.vcm_compute(idx, q, *bufs, precision=prec)
+                e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+            g = {"bin": bufs[0].cpu().numpy(), "c": bufs[1].cpu().numpy(),
+                 "count": bufs[2].cpu().numpy().view(np.uint16)}
+            leg[mname] = {"viewpoints_per_s": n * steps / wall, "rays_per_s": st["rays"] * steps / wall,
+                          "kernel_ms": kms, "rays_per_map": st["rays"]}
+            samples.append((leg[mname], scene, q, vp, {k: v[vp] for k, v in g.items()}))
+        idx.free()
+        out[name] = leg
+    return out, samples
 
 
 def bench_pruned(vcm, idx, q):
@@ -516,6 +567,11 @@ def main():
             print(f"pruned ({mname}): brute {leg['brute_ms']:.2f} ms, " +
                   ", ".join(f"{k} {v['ms']:.2f} ms" for k, v in leg["methods"].items()),
                   file=sys.stderr, flush=True)
+    config_samples = []
+    if not (args.no_configs or args.no_extra):
+        extra["configs"], config_samples = bench_configs(max(2, args.steps // 2))
+        print("configs: " + ", ".join(f"{k} {v['full']['viewpoints_per_s'] / 1e6:.0f} M vp/s (full)"
+                                      for k, v in extra["configs"].items()), file=sys.stderr, flush=True)
     if not (args.no_index or args.no_extra):
         extra["index_build"] = bench_index()
     if not (args.no_sweeps or args.no_extra):
@@ -550,6 +606,10 @@ def main():
         extra["cpu_baseline_all_cores"] = {"value": len(vp) / dt_all, "unit": "viewpoints/s",
                                            "cores": ncores, "nproc": os.cpu_count(), "kind": "oracle",
                                            "sample": f"the same {len(vp)} viewpoints, {ncores} threads"}
+        # the smaller configurations' maps against the oracle on their samples
+        for leg, sc, qc, vpc, gs in config_samples:
+            leg["oracle_agreement"] = oracle_agreement(gs, oracle.vcm_eval(sc, qc, vpc, nthreads=ncores),
+                                                       qc.params.n_bins)
 
     line = {
         "metric": "VCM viewpoints/s (brute-force map, 3D city)",

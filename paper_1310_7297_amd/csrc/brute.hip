@@ -255,14 +255,35 @@ __device__ __attribute__((always_inline)) inline void corridor_walk(
                             dl[k] = R.lo[k] - q[k];
                             dh[k] = R.hi[k] - q[k];
                         }
+                        // a candidate's corners relative to q, from its
+                        // lane through the LDS crossbar (ds_bpermute) rather
+                        // than six v_readlane: the vector ALU is the
+                        // kernel's limit and the crossbar is idle
+                        auto fetch = [&](int r, float (&lq)[3], float (&hq)[3]) {
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) {
+                                lq[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(r << 2, __float_as_int(dl[k])));
+                                hq[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(r << 2, __float_as_int(dh[k])));
+                            }
+                        };
+                        // FULL mode fetches one candidate ahead (measured
+                        // faster; in FRACTION mode the registers it holds
+                        // cost more than the wait it hides)
+                        float nlq[3], nhq[3];
+                        if constexpr (MODE == VCM_FULL) fetch(__builtin_ctzll(cand), nlq, nhq);
                         do {
                             const int r = __builtin_ctzll(cand);
                             cand &= cand - 1;
                             float blq[3], bhq[3];
+                            if constexpr (MODE == VCM_FULL) {
 #pragma unroll
-                            for (int k = 0; k < 3; ++k) {
-                                blq[k] = readlane_f(dl[k], r);
-                                bhq[k] = readlane_f(dh[k], r);
+                                for (int k = 0; k < 3; ++k) {
+                                    blq[k] = nlq[k];
+                                    bhq[k] = nhq[k];
+                                }
+                                if (cand) fetch(__builtin_ctzll(cand), nlq, nhq);
+                            } else {
+                                fetch(r, blq, bhq);
                             }
                             const unsigned long long rest = box_test<DIM, NS, EXACT64, MODE, STATS, TAB>(
                                 blq, bhq, T, P, q, faces, tab, iv, sidx, open, zmask, ws, n_disagree);
@@ -962,7 +983,15 @@ vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_
                         DevStats *stats, uint32_t *gate, int theta, const Tuning &tune,
                         unsigned *counter, int fill) {
     if (g_in.count <= 0) return VCM_OK;
-    BruteArgs a = make_brute_args(ix, t, g_in, p, r, gate, theta, chunk_for(tune, p.mode));
+    const int cus = device_cus(ix.device);
+    // viewpoints per work item: the mode's run length, halved while a small
+    // map would give fewer work items than the device has SIMDs
+    int chunk = chunk_for(tune, p.mode);
+    if (tune.chunk <= 0) {
+        const int64_t rows = int64_t(g_in.n[1]) * std::max(1, g_in.n[2]);
+        while (chunk > 1 && (g_in.n[0] + chunk - 1) / chunk * rows < int64_t(cus) * 4) chunk /= 2;
+    }
+    BruteArgs a = make_brute_args(ix, t, g_in, p, r, gate, theta, chunk);
     a.stats = stats;
     a.fill = gate && theta == 1 && fill ? 1 : 0;
     const int ns = slots_for(t);
@@ -973,7 +1002,6 @@ vcm_status launch_brute(const Index &ix, const TargetDesc &t, const GridDesc &g_
     const int64_t rows_per_layer = g.n[1];
     // launches over z slabs keep the work-item count within 32 bits
     const int64_t max_layers = std::max<int64_t>(1, (int64_t(1) << 30) / (cpr * rows_per_layer));
-    const int cus = device_cus(ix.device);
     for (int64_t k0 = 0; k0 < g.n[2]; k0 += max_layers) {
         const int64_t nl = std::min<int64_t>(max_layers, g.n[2] - k0);
         a.k_begin = static_cast<int32_t>(k0);
