@@ -726,6 +726,7 @@ struct LeafArgs {
     unsigned *claim;        // work counter (cleared)
     int32_t side;           // viewpoints per block edge
     int32_t nb[3];          // blocks per axis
+    int32_t run;            // entries a wavefront claims at once
 };
 
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
@@ -744,19 +745,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE
     WaveStats ws;
     unsigned long long n_disagree = 0, n_leaves = 0;
     const unsigned n_in = *LA.count;
-    // A wavefront claims a run of kLeafRun consecutive entries: the octants
+    // A wavefront claims LA.run consecutive entries at once: the sub-blocks
     // an undecided block hands down sit next to each other in the list, so
     // the box that blocked one leaf (FULL mode) is tried first on the next.
+    const unsigned run = static_cast<unsigned>(LA.run);
     int blk = -1;
     unsigned item = 0, end = 0;
     for (;;) {
         if (item >= end) {
             unsigned first = 0;
-            if (lane == 0) first = atomicAdd(LA.claim, static_cast<unsigned>(kLeafRun));
+            if (lane == 0) first = atomicAdd(LA.claim, run);
             first = __builtin_amdgcn_readfirstlane(__shfl(first, 0));
             if (first >= n_in) break;
             item = first;
-            end = min(n_in, first + static_cast<unsigned>(kLeafRun));
+            end = min(n_in, first + run);
         }
         const uint32_t b = LA.list[item++];
         const int bi[3] = {static_cast<int>(b % static_cast<uint32_t>(LA.nb[0])),
@@ -950,6 +952,12 @@ vcm_status launch_leaves(const Index &ix, const TargetDesc &t, const GridDesc &g
     la.claim = claim;
     la.side = bp.leaf;
     for (int k = 0; k < 3; ++k) la.nb[k] = k < ix.dim ? (g.n[k] + bp.leaf - 1) / bp.leaf : 1;
+    // leaves listed with their siblings (the smallest blocks inside an
+    // undecided classified block) go in runs, for the blocker cache; leaves
+    // that are the classified blocks themselves have no such neighbours and
+    // go one by one, which spreads a short list over the device (measured:
+    // FRACTION, theta 8: 0.96 -> 0.88 ms; theta 16: 1.78 -> 1.66 ms)
+    la.run = bp.leaf < bp.side[bp.classified - 1] ? kLeafRun : 1;
     const int64_t nleaf = bp.count[bp.levels - 1];
     const dim3 grid(static_cast<unsigned>(
         std::max<int64_t>(1, std::min<int64_t>((nleaf + 3) / 4, int64_t(device_cus(ix.device)) * 8))));
