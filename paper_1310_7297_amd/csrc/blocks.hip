@@ -74,6 +74,58 @@ __device__ inline bool hull_meets(const float *L, const float *H, const float *s
     return ok && ln * ud <= un * ld;
 }
 
+// Float32 filters for the two hull tests: 1 when the hull surely meets the
+// box, 0 when it surely misses, -1 when the float32 bounds on lambda lie
+// within kHullEps of each other, where the exact test decides.  Each bound
+// y / x is y * rcp(x) with x and y exact differences, within 1.5 * 2^-23
+// relative (1 ulp for the reciprocal, half an ulp for the product); a bound
+// beyond [-2, 2] decides nothing near the margin (min(1, .) and max(0, .)
+// clip it, or the gap is then below -1), so every bound that matters is off
+// by less than 2^-21, inside kHullEps.
+constexpr float kHullEps = 0x1p-20f;
+
+template <int DIM>
+__device__ inline int hull_meets_f32(const float *L, const float *H, const float *s, const float *a,
+                                     const float *c) {
+    float lo = 0.0f, hi = 1.0f;
+    bool fail = false;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const float x = side ? s[k] - H[k] : L[k] - s[k];
+            const float y = side ? s[k] - a[k] : c[k] - s[k];
+            const float t = y * __builtin_amdgcn_rcpf(x);
+            if (x > 0.0f) hi = fminf(hi, t);
+            else if (x < 0.0f) lo = fmaxf(lo, t);
+            else fail = fail || y < 0.0f;
+        }
+    if (fail) return 0;
+    const float gap = hi - lo;
+    return gap > kHullEps ? 1 : (gap < -kHullEps ? 0 : -1);
+}
+
+template <int DIM>
+__device__ inline int hull2_meets_f32(const float *L, const float *H, const float *F0, const float *F1,
+                                      const float *a, const float *c) {
+    float lo = 0.0f, hi = 1.0f;
+    bool fail = false;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const float x = side ? H[k] - F1[k] : F0[k] - L[k];
+            const float y = side ? H[k] - a[k] : c[k] - L[k];
+            const float t = y * __builtin_amdgcn_rcpf(x);
+            if (x > 0.0f) hi = fminf(hi, t);
+            else if (x < 0.0f) lo = fmaxf(lo, t);
+            else fail = fail || y < 0.0f;
+        }
+    if (fail) return 0;
+    const float gap = hi - lo;
+    return gap > kHullEps ? 1 : (gap < -kHullEps ? 0 : -1);
+}
+
 // Exact: does the closed box [a, c] meet the convex hull of the boxes [L, H]
 // and [F0, F1]?  That hull is the union over lambda in [0, 1] of the boxes
 // [L + lambda (F0 - L), H + lambda (F1 - H)]; per axis, two linear
@@ -139,7 +191,7 @@ __device__ inline float vp_pos(const GridDesc &g, int k, int i) {
 // candidate's corners and returns true to stop the walk.  Float32 with the
 // same margins as the viewpoint corridor: the walk never drops a column or
 // record the hull reaches (records are inserted with a 2^-6 m margin).
-template <int DIM, int AX, class Visit>
+template <int DIM, int AX, bool FAST, class Visit>
 __device__ inline void block_walk(const BlockLevel &B, cptr_i32 col_start, cptr_rec recs, const float (&L)[3],
                                   const float (&H)[3], Visit &&visit) {
     const TargetDesc &T = B.tgt;
@@ -195,7 +247,14 @@ __device__ inline void block_walk(const BlockLevel &B, cptr_i32 col_start, cptr_
                 bool cand = above && R.id >= 0 && R.hi[BX] >= bl && R.lo[BX] <= bh && (DIM == 2 || R.lo[2] <= zc);
                 // exactly: only a box that meets the hull of the block and the
                 // target's box can meet a line of sight from the block
-                if (cand) cand = hull2_meets<DIM>(L, H, F0, F1, R.lo, R.hi);
+                if (cand) {
+                    if constexpr (FAST) {
+                        const int f = hull2_meets_f32<DIM>(L, H, F0, F1, R.lo, R.hi);
+                        cand = f > 0 || (f < 0 && hull2_meets<DIM>(L, H, F0, F1, R.lo, R.hi));
+                    } else {
+                        cand = hull2_meets<DIM>(L, H, F0, F1, R.lo, R.hi);
+                    }
+                }
                 unsigned long long cm = __ballot(cand);
                 const unsigned long long below = __ballot(!above);
                 while (cm) {
@@ -355,7 +414,12 @@ __global__ __launch_bounds__(256) void k_blocks(BlockLevel B, const int32_t *col
                         if (!todo) continue;
                         bool meet = false, hid = false;
                         if ((todo >> lane) & 1) {
-                            meet = hull_meets<DIM>(L, H, sp[j], a, c);
+                            if constexpr (MODE == VCM_FRACTION) {
+                                const int f = hull_meets_f32<DIM>(L, H, sp[j], a, c);
+                                meet = f > 0 || (f < 0 && hull_meets<DIM>(L, H, sp[j], a, c));
+                            } else {
+                                meet = hull_meets<DIM>(L, H, sp[j], a, c);
+                            }
                             if (meet) {
                                 // hidden from the whole block if the box cuts
                                 // the segment from every corner to the sample
@@ -391,8 +455,8 @@ __global__ __launch_bounds__(256) void k_blocks(BlockLevel B, const int32_t *col
                     return false;
                 };
                 const float dx = fabsf(T.c[0] - 0.5f * (L[0] + H[0])), dy = fabsf(T.c[1] - 0.5f * (L[1] + H[1]));
-                if (dx >= dy) block_walk<DIM, 0>(B, col_start, recs, L, H, visit);
-                else block_walk<DIM, 1>(B, col_start, recs, L, H, visit);
+                if (dx >= dy) block_walk<DIM, 0, MODE == VCM_FRACTION>(B, col_start, recs, L, H, visit);
+                else block_walk<DIM, 1, MODE == VCM_FRACTION>(B, col_start, recs, L, H, visit);
                 (void)stop;
                 int n_seen = 0, n_hidden = 0;
 #pragma unroll
