@@ -55,7 +55,7 @@ def test_plain2d_full_map(method, mode, theta):
 
 @pytest.mark.parametrize("method", [1, 2, 3])
 @pytest.mark.parametrize("kind", [BILLBOARD, CUBE])
-@pytest.mark.parametrize("theta", [1, 2, 4])
+@pytest.mark.parametrize("theta", [1, 2, 4, 8])
 @pytest.mark.parametrize("mode", [FULL, FRACTION])
 def test_small_3d_full_map(method, kind, theta, mode):
     """Whole maps against the oracle, the visible-region blocks included.
