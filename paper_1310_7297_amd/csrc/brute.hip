@@ -620,11 +620,11 @@ __device__ inline void flush_stats(DevStats *st, const WaveStats &ws, unsigned l
 }
 
 // Occupancy target of the ray kernels (waves per SIMD): the register budget
-// it leaves decides how much the compiler spills.  FULL mode gains from the
-// seventh wave; FRACTION mode, whose walk keeps more rays and masks live,
-// spills to scratch memory at seven.
+// it leaves decides how much the compiler spills.  Six in both modes
+// (measured against five and seven: five leaves too few waves to hide the
+// walk's latencies, seven spills more than the extra wave gains).
 template <int MODE>
-constexpr int kWaves = MODE == VCM_FULL ? 7 : 6;
+constexpr int kWaves = 6;
 
 // One query: persistent wavefronts take the query's work items.
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
