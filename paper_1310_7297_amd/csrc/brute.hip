@@ -622,9 +622,14 @@ __device__ inline void flush_stats(DevStats *st, const WaveStats &ws, unsigned l
 // Occupancy target of the ray kernels (waves per SIMD): the register budget
 // it leaves decides how much the compiler spills.  Six in both modes
 // (measured against five and seven: five leaves too few waves to hide the
-// walk's latencies, seven spills more than the extra wave gains).
+// walk's latencies, seven spills more than the extra wave gains).  The
+// batched kernel, whose FULL-mode queries are mostly small maps, keeps a
+// seventh wave in FULL mode (measured: 5.3 G viewpoints/s at six, 5.6 G at
+// seven).
 template <int MODE>
 constexpr int kWaves = 6;
+template <int MODE>
+constexpr int kBatchWaves = MODE == VCM_FULL ? 7 : 6;
 
 // One query: persistent wavefronts take the query's work items.
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
@@ -657,7 +662,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE
 // found by binary search over the queries' group ends; its record is read
 // from constant memory (scalar loads).
 template <int DIM, int NS, bool EXACT64, int MODE, bool STATS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<MODE>, 8))) void k_brute_batch(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBatchWaves<MODE>, 8))) void k_brute_batch(
     BatchArgs B, const BruteArgs *qs_g, const uint32_t *group_end_g, const int32_t *col_start_g,
     const BoxRec *recs_g) {
     const cptr_i32 col_start = (cptr_i32)col_start_g;
