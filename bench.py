@@ -37,11 +37,11 @@ PEAK_HBM = 8.0e12
 # FETCH_SIZE / WRITE_SIZE summary (copy-kernel calibrated), valid only for the
 # kernel sources it was taken on.
 PROFILE = os.path.join(ROOT, "profiles", "k_brute_city20k_cube_fraction.md")
-TRAFFIC_BYTES = 138572614
+TRAFFIC_BYTES = 139207458
 TRAFFIC_CELL = 128.0
 KERNEL_SOURCES = ("brute.hip", "trace_common.h", "index.hip", "vcm_internal.h")
 # Issue counters of the same profile (per launch), valid under the same hash.
-PROFILE_VALU = {"fraction": 2.685e9, "full": 5.560e8}
+PROFILE_VALU = {"fraction": 2.685e9, "full": 5.313e8}
 CUS, CLOCK = 256, 2.4e9
 
 
